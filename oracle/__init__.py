@@ -1,0 +1,26 @@
+"""CPU oracle for the Binary Stereo Matching hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It is a thin ctypes
+wrapper over ``liboracle.so`` (built from ``bsm_oracle.c``), which is a plain
+CPU definition of Zhang et al., "Binary Stereo Matching", Section 3,
+Eq. 1-8.  It shares no code with the GPU library.
+"""
+from .oracle import (  # noqa: F401
+    INVALID_COST,
+    cost_volume,
+    describe,
+    lab8,
+    lab8_tables,
+    load,
+    luma,
+    make_pattern,
+    mask,
+    match,
+    normal_draws,
+    set_threads,
+    get_threads,
+    splitmix64,
+    weights,
+    wta,
+)
