@@ -1,0 +1,210 @@
+/*
+ * bsm.h - C ABI of the MI355X (gfx950) Binary Stereo Matching library.
+ *
+ * The library computes the hot path of Zhang et al., "Binary Stereo
+ * Matching" (Section 3): a BRIEF descriptor per pixel of both views
+ * (Eq. 2-3), a binary support mask for the reference view (Eq. 5-7), the
+ * masked Hamming cost by XOR / AND / popcount on packed words (Eq. 8; Eq. 4
+ * without the mask) and the winner-take-all disparity over
+ * d in [0, dmax - 1] (Eq. 1).  Input: a rectified RGB pair and dmax, as in
+ * the problem statement of Section 1; output: an integer disparity map and,
+ * on request, the cost volume.  Every step runs in HIP kernels on the GPU.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Views      The left view is the reference; pixel x = (u, v) of the left
+ *            view is compared with x_d = (u - d, v) of the right view.
+ * Images     uint8 RGB, interleaved, rows `stride` bytes apart
+ *            (stride >= 3 * W).
+ * Intensity  I = (77 R + 150 G + 29 B + 128) >> 8 (the paper says only
+ *            "intensity"; this is integer BT.601 luma).
+ * CIELAB     8-bit L8 = L*255/100, a8 = a + 128, b8 = b + 128 for sRGB with
+ *            the D65 white, computed with integer tables (the paper names
+ *            the colour space only).
+ * Borders    A sample outside the image takes the nearest edge pixel.
+ * Pattern    int8 [n][4] rows (px, py, qx, qy): pair i compares
+ *            x + (px, py) with x + (qx, qy) (Section 3, after Eq. 2).
+ * Bits       Pair i (1-based) is bit (i-1) % 64 of word (i-1) / 64: the
+ *            weight 2^(i-1) of Eq. 2 and Eq. 7.
+ * desc/mask  uint64 [H][W][n/64], pixel-major ("words of pixel (u, v)
+ *            start at ((v * W) + u) * n/64").
+ * Threshold  T(x) = k-th smallest pair weight, k = n/4 by default (the
+ *            "quarter smallest value" after Eq. 6); delta_i = [w_i <= T].
+ * Cost       C(x, d) = popcount((B_L(x) XOR B_R(x_d)) AND Phi(x)); with no
+ *            mask, popcount(B_L(x) XOR B_R(x_d)).  C <= n.
+ * Volume     int16 [dmax][H][W]; entries with u - d < 0 hold 32767.
+ * Disparity  int32 [H][W]: the smallest d that attains min_d C(x, d).
+ *
+ * Pointers   "device" = memory of the context's GPU (e.g. a torch CUDA
+ *            tensor's data_ptr()); "host" = ordinary CPU memory.  Device
+ *            calls take a HIP stream (hipStream_t, NULL = default stream),
+ *            are stream-ordered and return once the work is enqueued.
+ *            Device buffers must be 8-byte aligned (desc/mask/disp/cost) and
+ *            must not overlap.  The caller owns every buffer it passes.
+ * Errors     Every call returns a status and never aborts.  Arguments are
+ *            validated before any device work (BSM_EINVAL).  A failed HIP
+ *            call returns BSM_EDEVICE and marks the context dead: every
+ *            later call on it returns BSM_EDEVICE.  bsm_last_error() gives a
+ *            message for the calling thread's last failure.
+ * Threads    A context may be used from one thread at a time, except
+ *            bsm_submit / bsm_poll / bsm_drain, which lock internally.
+ */
+#ifndef BSM_H
+#define BSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSM_OK = 0,
+    BSM_EINVAL = -1,    /* invalid argument; nothing was enqueued          */
+    BSM_ENOMEM = -2,    /* device or host allocation failed                */
+    BSM_EDEVICE = -3,   /* HIP error (sticky on the context)               */
+    BSM_EAGAIN = -4,    /* serving queue full; try again later             */
+    BSM_ETOOBIG = -5,   /* pair larger than the serving admission cap      */
+    BSM_ENOTFOUND = -6  /* unknown ticket                                  */
+} bsm_status;
+
+typedef struct bsm_ctx bsm_ctx;
+
+typedef struct {
+    int32_t n_bits;         /* n: descriptor length, multiple of 64 in
+                               [64, 4096] (the paper uses 4096, Section 4.1) */
+    int32_t window;         /* S: side of the sampling window, 2..63
+                               (the paper uses 26); offsets lie in
+                               [-S/2, (S-1)/2]                              */
+    double sigma;           /* spread of the Gaussian sampling; <= 0 selects
+                               4 * S / 26 (the paper's 4 at S = 26)         */
+    uint64_t seed;          /* seed for the pattern when pattern == NULL    */
+    const int8_t *pattern;  /* host [n][4] pattern to use, or NULL to draw
+                               one with bsm_make_pattern(seed, ...); copied */
+    int32_t mask_rank;      /* k of the threshold, 1..n; 0 selects n/4      */
+    int32_t use_mask;       /* bsm_match / batch / serving: 1 = Eq. 8
+                               (masked cost), 0 = Eq. 4 (plain Hamming)     */
+} bsm_params;
+
+/* One stereo pair for bsm_match_batch (device pointers) or bsm_submit
+ * (host pointers). */
+typedef struct {
+    const uint8_t *left;    /* RGB [H][stride]                              */
+    const uint8_t *right;   /* RGB [H][stride]                              */
+    int32_t width, height, stride, dmax;
+    int32_t *disp;          /* out int32 [H][W]                             */
+    int16_t *cost;          /* out int16 [dmax][H][W], or NULL              */
+} bsm_pair;
+
+/* Serving timestamps, seconds on the host's CLOCK_MONOTONIC. */
+typedef struct {
+    double t_arrive;        /* bsm_submit was called                        */
+    double t_admit;         /* admitted under the memory cap                */
+    double t_start;         /* its first GPU work was enqueued              */
+    double t_end;           /* results were in host memory                  */
+} bsm_times;
+
+/* Creates a context on HIP device `hip_device`: validates the parameters,
+ * copies or draws the point-pair pattern (Section 3, after Eq. 2), builds
+ * the integer colour tables and uploads both.  On success *out owns them.
+ * BSM_EINVAL on bad parameters, BSM_EDEVICE / BSM_ENOMEM on HIP failure. */
+bsm_status bsm_create(const bsm_params *params, int32_t hip_device,
+                      bsm_ctx **out);
+
+/* Waits for the context's in-flight work, stops its serving thread and
+ * frees everything it owns.  NULL is ignored. */
+void bsm_destroy(bsm_ctx *ctx);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *bsm_last_error(void);
+
+/* Host only: draws the pattern of Section 3 (after Eq. 2): each of the
+ * 4 n coordinates is floor(sigma * z + 0.5), z a standard normal from the
+ * basic Box-Muller transform of two splitmix64 outputs (seeded with `seed`),
+ * redrawn while outside [-S/2, (S-1)/2]; q is redrawn while q == p.
+ * out: host int8 [n][4].  n in [1, 4096], S in [2, 63], sigma > 0. */
+bsm_status bsm_make_pattern(uint64_t seed, int32_t n, int32_t S, double sigma,
+                            int8_t *out);
+
+/* Copies the context's pattern to host int8 [n][4]. */
+bsm_status bsm_pattern(const bsm_ctx *ctx, int8_t *out);
+
+/* Device bytes bsm_match needs for one W x H pair (its internal scratch:
+ * colour planes and descriptors), plus the volume if want_cost.  0 on
+ * invalid arguments. */
+size_t bsm_footprint(const bsm_ctx *ctx, int32_t W, int32_t H, int32_t dmax,
+                     int32_t want_cost);
+
+/* Colour pre-pass (the intensity of Eq. 3 and the CIELAB values of Eq. 5):
+ * packed uint32 [H][W], byte 0 = L8, 1 = a8, 2 = b8, 3 = I.  With
+ * want_lab == 0 bytes 0-2 are 0.  img: device RGB; packed: device. */
+bsm_status bsm_color(bsm_ctx *ctx, const uint8_t *img, int32_t W, int32_t H,
+                     int32_t stride, uint32_t *packed, int32_t want_lab,
+                     void *hip_stream);
+
+/* Descriptor B (Eq. 2-3) of every pixel of one view, and its binary mask Phi
+ * (Eq. 5-7) when mask != NULL (the reference view).  img: device RGB;
+ * desc, mask: device uint64 [H][W][n/64].  Uses context scratch. */
+bsm_status bsm_describe(bsm_ctx *ctx, const uint8_t *img, int32_t W,
+                        int32_t H, int32_t stride, uint64_t *desc,
+                        uint64_t *mask, void *hip_stream);
+
+/* Descriptor and optional mask from the colour pre-pass output (bsm_color
+ * with want_lab = 1 when mask != NULL): the same as bsm_describe without its
+ * colour step.  packed: device uint32 [H][W]; desc, mask as bsm_describe. */
+bsm_status bsm_describe_packed(bsm_ctx *ctx, const uint32_t *packed, int32_t W,
+                               int32_t H, uint64_t *desc, uint64_t *mask,
+                               void *hip_stream);
+
+/* Masked cost (Eq. 8, or Eq. 4 when maskL == NULL) fused with the
+ * winner-take-all of Eq. 1.  The H x W x dmax volume is written only when
+ * cost != NULL.  descL, maskL, descR: device uint64 [H][W][n/64];
+ * disp: device int32 [H][W]; cost: device int16 [dmax][H][W] or NULL.
+ * 1 <= dmax <= W. */
+bsm_status bsm_cost_wta(bsm_ctx *ctx, const uint64_t *descL,
+                        const uint64_t *maskL, const uint64_t *descR,
+                        int32_t W, int32_t H, int32_t dmax, int32_t *disp,
+                        int16_t *cost, void *hip_stream);
+
+/* The whole hot path for one pair: colour pre-pass and descriptors of both
+ * views, mask of the left view (if params.use_mask), cost and WTA.
+ * left/right: device RGB; disp/cost as in bsm_cost_wta.  Uses context
+ * scratch (bsm_footprint bytes). */
+bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
+                     int32_t W, int32_t H, int32_t stride, int32_t dmax,
+                     int32_t *disp, int16_t *cost, void *hip_stream);
+
+/* Many pairs of uneven size and dmax in one persistent launch over a device
+ * work queue (captured once per batch shape into a HIP graph and replayed).
+ * All pointers in `pairs` are device pointers; `pairs` itself is host
+ * memory.  Results equal npairs calls of bsm_match. */
+bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs,
+                           int32_t npairs, void *hip_stream);
+
+/* Serving: admission cap on the device working set of pairs in flight
+ * (bytes; default 32 GiB) and the maximum number of queued requests. */
+bsm_status bsm_serve_config(bsm_ctx *ctx, size_t cap_bytes, int32_t max_queue);
+
+/* Serving: queues one pair given in HOST memory and returns a ticket.  The
+ * library copies the images to the device when the pair is admitted and
+ * writes disp (and cost) back to the host buffers; the caller keeps all
+ * four buffers alive until bsm_poll reports it done or failed.
+ * BSM_ETOOBIG if the pair alone exceeds the cap, BSM_EAGAIN if the queue is
+ * full. */
+bsm_status bsm_submit(bsm_ctx *ctx, const bsm_pair *pair, uint64_t *ticket);
+
+/* Serving: state of a ticket (0 pending, 1 done, -1 failed) and its
+ * timestamps (times may be NULL).  A done or failed ticket is forgotten
+ * after it is reported once.  BSM_ENOTFOUND for unknown tickets. */
+bsm_status bsm_poll(bsm_ctx *ctx, uint64_t ticket, int32_t *state,
+                    bsm_times *times);
+
+/* Serving: blocks until every submitted pair is done or failed. */
+bsm_status bsm_drain(bsm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSM_H */

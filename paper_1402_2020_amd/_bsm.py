@@ -1,0 +1,296 @@
+"""ctypes binding of libbsm.so (include/bsm.h).
+
+The functions below carry the C names and only marshal arguments; every
+step of the matching runs in the library's HIP kernels.  ``Context`` adds a
+thin convenience layer that allocates outputs as torch CUDA tensors (torch is
+used for device memory and streams only).
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsm.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETOOBIG, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "BSM_OK", -1: "BSM_EINVAL", -2: "BSM_ENOMEM", -3: "BSM_EDEVICE",
+                -4: "BSM_EAGAIN", -5: "BSM_ETOOBIG", -6: "BSM_ENOTFOUND"}
+INVALID_COST = 32767
+
+# Every symbol include/bsm.h declares.
+EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
+           "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
+           "bsm_match_batch", "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain")
+
+
+class BsmError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {bsm_last_error()}")
+
+
+class Params(C.Structure):
+    _fields_ = [("n_bits", C.c_int32), ("window", C.c_int32), ("sigma", C.c_double),
+                ("seed", C.c_uint64), ("pattern", C.POINTER(C.c_int8)),
+                ("mask_rank", C.c_int32), ("use_mask", C.c_int32)]
+
+
+class Pair(C.Structure):
+    _fields_ = [("left", C.c_void_p), ("right", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("stride", C.c_int32), ("dmax", C.c_int32),
+                ("disp", C.c_void_p), ("cost", C.c_void_p)]
+
+
+class Times(C.Structure):
+    _fields_ = [("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_start", C.c_double),
+                ("t_end", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libbsm.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, u64, sz = C.c_void_p, C.c_int32, C.c_uint64, C.c_size_t
+    st = C.c_int
+    sig = {
+        "bsm_create": ([C.POINTER(Params), i32, C.POINTER(vp)], st),
+        "bsm_destroy": ([vp], None),
+        "bsm_last_error": ([], C.c_char_p),
+        "bsm_make_pattern": ([u64, i32, i32, C.c_double, C.POINTER(C.c_int8)], st),
+        "bsm_pattern": ([vp, C.POINTER(C.c_int8)], st),
+        "bsm_footprint": ([vp, i32, i32, i32, i32], sz),
+        "bsm_color": ([vp, vp, i32, i32, i32, vp, i32, vp], st),
+        "bsm_describe": ([vp, vp, i32, i32, i32, vp, vp, vp], st),
+        "bsm_describe_packed": ([vp, vp, i32, i32, vp, vp, vp], st),
+        "bsm_cost_wta": ([vp, vp, vp, vp, i32, i32, i32, vp, vp, vp], st),
+        "bsm_match": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
+        "bsm_match_batch": ([vp, C.POINTER(Pair), i32, vp], st),
+        "bsm_serve_config": ([vp, sz, i32], st),
+        "bsm_submit": ([vp, C.POINTER(Pair), C.POINTER(u64)], st),
+        "bsm_poll": ([vp, u64, C.POINTER(i32), C.POINTER(Times)], st),
+        "bsm_drain": ([vp], st),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != OK:
+        raise BsmError(status, what)
+
+
+# ---- the C entry points, same names -------------------------------------
+
+def bsm_last_error():
+    return load().bsm_last_error().decode()
+
+
+def bsm_make_pattern(seed, n, S, sigma):
+    import numpy as np
+    out = np.zeros((n, 4), np.int8)
+    _check(load().bsm_make_pattern(seed, n, S, float(sigma),
+                                   out.ctypes.data_as(C.POINTER(C.c_int8))), "bsm_make_pattern")
+    return out
+
+
+def bsm_create(n_bits, window, sigma=0.0, seed=0, pattern=None, mask_rank=0, use_mask=1,
+               device=0):
+    import numpy as np
+    p = Params(n_bits, window, float(sigma), seed, None, mask_rank, int(use_mask))
+    keep = None
+    if pattern is not None:
+        keep = np.ascontiguousarray(pattern, dtype=np.int8)
+        p.pattern = keep.ctypes.data_as(C.POINTER(C.c_int8))
+    h = C.c_void_p()
+    _check(load().bsm_create(C.byref(p), device, C.byref(h)), "bsm_create")
+    return h
+
+
+def bsm_destroy(ctx):
+    load().bsm_destroy(ctx)
+
+
+def bsm_pattern(ctx, n):
+    import numpy as np
+    out = np.zeros((n, 4), np.int8)
+    _check(load().bsm_pattern(ctx, out.ctypes.data_as(C.POINTER(C.c_int8))), "bsm_pattern")
+    return out
+
+
+def bsm_footprint(ctx, W, H, dmax, want_cost):
+    return load().bsm_footprint(ctx, W, H, dmax, int(want_cost))
+
+
+def bsm_color(ctx, img, W, H, stride, packed, want_lab, stream):
+    return load().bsm_color(ctx, img, W, H, stride, packed, int(want_lab), stream)
+
+
+def bsm_describe(ctx, img, W, H, stride, desc, mask, stream):
+    return load().bsm_describe(ctx, img, W, H, stride, desc, mask, stream)
+
+
+def bsm_describe_packed(ctx, packed, W, H, desc, mask, stream):
+    return load().bsm_describe_packed(ctx, packed, W, H, desc, mask, stream)
+
+
+def bsm_cost_wta(ctx, descL, maskL, descR, W, H, dmax, disp, cost, stream):
+    return load().bsm_cost_wta(ctx, descL, maskL, descR, W, H, dmax, disp, cost, stream)
+
+
+def bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
+    return load().bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream)
+
+
+def bsm_match_batch(ctx, pairs, stream):
+    arr = (Pair * len(pairs))(*pairs)
+    return load().bsm_match_batch(ctx, arr, len(pairs), stream)
+
+
+def bsm_serve_config(ctx, cap_bytes, max_queue):
+    return load().bsm_serve_config(ctx, cap_bytes, max_queue)
+
+
+def bsm_submit(ctx, pair):
+    t = C.c_uint64()
+    st = load().bsm_submit(ctx, C.byref(pair), C.byref(t))
+    return st, t.value
+
+
+def bsm_poll(ctx, ticket):
+    state = C.c_int32()
+    times = Times()
+    st = load().bsm_poll(ctx, ticket, C.byref(state), C.byref(times))
+    return st, state.value, times
+
+
+def bsm_drain(ctx):
+    return load().bsm_drain(ctx)
+
+
+# ---- convenience layer over torch tensors --------------------------------
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns a bsm_ctx.  Images are uint8 CUDA tensors [H][W][3]; descriptor
+    and mask tensors are int64 [H][W][n/64] holding the uint64 words."""
+
+    def __init__(self, n_bits, window, sigma=0.0, seed=0, pattern=None, mask_rank=0,
+                 use_mask=True, device=0):
+        self.n = n_bits
+        self.nw = n_bits // 64
+        self.device = device
+        self.use_mask = bool(use_mask)
+        self.h = bsm_create(n_bits, window, sigma, seed, pattern, mask_rank, use_mask, device)
+
+    def close(self):
+        if self.h is not None:
+            bsm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pattern(self):
+        return bsm_pattern(self.h, self.n)
+
+    def footprint(self, W, H, dmax, want_cost=False):
+        return bsm_footprint(self.h, W, H, dmax, want_cost)
+
+    @staticmethod
+    def _img(img):
+        if img.dtype.itemsize != 1 or img.dim() != 3 or img.shape[2] != 3 or not img.is_cuda:
+            raise ValueError("image must be a uint8 CUDA tensor [H][W][3]")
+        img = img.contiguous()
+        H, W, _ = img.shape
+        return img, W, H, 3 * W
+
+    def color(self, img, want_lab=True, stream=None):
+        import torch
+        img, W, H, st = self._img(img)
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+        _check(bsm_color(self.h, _ptr(img), W, H, st, _ptr(out), want_lab, _stream(stream)),
+               "bsm_color")
+        return out
+
+    def describe(self, img, with_mask=False, stream=None):
+        import torch
+        img, W, H, st = self._img(img)
+        desc = torch.empty((H, W, self.nw), dtype=torch.int64, device=img.device)
+        mask = torch.empty_like(desc) if with_mask else None
+        _check(bsm_describe(self.h, _ptr(img), W, H, st, _ptr(desc), _ptr(mask),
+                            _stream(stream)), "bsm_describe")
+        return desc, mask
+
+    def describe_packed(self, packed, with_mask=False, stream=None):
+        import torch
+        H, W = packed.shape
+        desc = torch.empty((H, W, self.nw), dtype=torch.int64, device=packed.device)
+        mask = torch.empty_like(desc) if with_mask else None
+        _check(bsm_describe_packed(self.h, _ptr(packed), W, H, _ptr(desc), _ptr(mask),
+                                   _stream(stream)), "bsm_describe_packed")
+        return desc, mask
+
+    def cost_wta(self, descL, maskL, descR, dmax, want_cost=False, stream=None):
+        import torch
+        H, W, _ = descL.shape
+        disp = torch.empty((H, W), dtype=torch.int32, device=descL.device)
+        cost = torch.empty((dmax, H, W), dtype=torch.int16, device=descL.device) \
+            if want_cost else None
+        _check(bsm_cost_wta(self.h, _ptr(descL), _ptr(maskL), _ptr(descR), W, H, dmax,
+                            _ptr(disp), _ptr(cost), _stream(stream)), "bsm_cost_wta")
+        return disp, cost
+
+    def match(self, left, right, dmax, want_cost=False, disp=None, cost=None, stream=None):
+        import torch
+        left, W, H, st = self._img(left)
+        right, W2, H2, _ = self._img(right)
+        if (W2, H2) != (W, H):
+            raise ValueError("left and right must have the same shape")
+        if disp is None:
+            disp = torch.empty((H, W), dtype=torch.int32, device=left.device)
+        if cost is None and want_cost:
+            cost = torch.empty((dmax, H, W), dtype=torch.int16, device=left.device)
+        _check(bsm_match(self.h, _ptr(left), _ptr(right), W, H, st, dmax, _ptr(disp),
+                         _ptr(cost), _stream(stream)), "bsm_match")
+        return disp, cost
+
+    def match_batch(self, items, want_cost=False, stream=None):
+        """items: list of (left, right, dmax) CUDA tensors; returns a list of
+        (disp, cost)."""
+        import torch
+        pairs, outs, keep = [], [], []
+        for left, right, dmax in items:
+            left, W, H, st = self._img(left)
+            right, _, _, _ = self._img(right)
+            disp = torch.empty((H, W), dtype=torch.int32, device=left.device)
+            cost = torch.empty((dmax, H, W), dtype=torch.int16, device=left.device) \
+                if want_cost else None
+            keep += [left, right]
+            outs.append((disp, cost))
+            pairs.append(Pair(left.data_ptr(), right.data_ptr(), W, H, st, dmax,
+                              disp.data_ptr(), None if cost is None else cost.data_ptr()))
+        _check(bsm_match_batch(self.h, pairs, _stream(stream)), "bsm_match_batch")
+        return outs

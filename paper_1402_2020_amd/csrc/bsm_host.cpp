@@ -1,0 +1,485 @@
+// Host runtime of the BSM library: error plumbing, parameter validation,
+// the point-pair pattern, the integer colour tables, context lifetime and
+// the single-pair entry points.  All pixel work is done by the kernels in
+// bsm_kernels.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <ctime>
+
+#include "bsm_internal.h"
+
+namespace bsm {
+
+static thread_local std::string g_last_error;
+
+void clear_error() { g_last_error.clear(); }
+
+bsm_status fail(bsm_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+bsm_status device_fail(bsm_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();  // allocation failures are not sticky
+    return fail(BSM_ENOMEM, "%s: out of device memory", what);
+  }
+  if (ctx) {
+    ctx->dead = true;
+    ctx->dead_reason = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return fail(BSM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bsm_status check_alive(bsm_ctx *ctx) {
+  if (!ctx) return fail(BSM_EINVAL, "context is NULL");
+  if (ctx->dead)
+    return fail(BSM_EDEVICE, "context is dead after an earlier device error (%s)",
+                ctx->dead_reason.c_str());
+  return BSM_OK;
+}
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+bsm_status validate_image(const void *img, int W, int H, int stride) {
+  if (!img) return fail(BSM_EINVAL, "image pointer is NULL");
+  if (W < 1 || H < 1) return fail(BSM_EINVAL, "image size %dx%d must be positive", W, H);
+  if (W > kMaxSide || H > kMaxSide)
+    return fail(BSM_EINVAL, "image size %dx%d exceeds %d", W, H, kMaxSide);
+  if (stride < 3 * W) return fail(BSM_EINVAL, "stride %d < 3*W = %d", stride, 3 * W);
+  return BSM_OK;
+}
+
+bsm_status validate_dmax(int W, int dmax) {
+  if (dmax < 1 || dmax > W)
+    return fail(BSM_EINVAL, "dmax %d must be in [1, W=%d]", dmax, W);
+  if (dmax > 32767) return fail(BSM_EINVAL, "dmax %d too large", dmax);
+  return BSM_OK;
+}
+
+double now_seconds() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return ts.tv_sec + 1e-9 * ts.tv_nsec;
+}
+
+// RAII: makes the context's device current and restores the caller's.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) err_ = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
+  }
+  hipError_t err() const { return err_; }
+
+ private:
+  int prev_ = -1;
+  hipError_t err_ = hipSuccess;
+};
+
+// ---------------------------------------------------------------------------
+// Point-pair pattern (Section 3, after Eq. 2).  Coordinates are drawn from
+// splitmix64 (Steele, Lea and Flood, 2014) through the basic Box-Muller
+// transform (cosine branch): z = sqrt(-2 ln u1) cos(2 pi u2) with
+// u1 in (0, 1] and u2 in [0, 1) carrying 53 random bits each.  An offset is
+// floor(sigma z + 0.5), redrawn while outside [-S/2, (S-1)/2]; p is drawn
+// (x then y) before q, and q is redrawn while it equals p.
+// ---------------------------------------------------------------------------
+namespace {
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+double gaussian(SplitMix64 &g) {
+  const double two_pow_53 = 9007199254740992.0;
+  uint64_t x1 = g.next(), x2 = g.next();
+  double u1 = (double)((x1 >> 11) + 1) * (1.0 / two_pow_53);
+  double u2 = (double)(x2 >> 11) * (1.0 / two_pow_53);
+  double r = std::sqrt(-2.0 * std::log(u1));
+  return r * std::cos(6.283185307179586 * u2);
+}
+
+int offset_in_window(SplitMix64 &g, double sigma, int lo, int hi) {
+  while (true) {
+    double o = std::floor(sigma * gaussian(g) + 0.5);
+    if (o >= lo && o <= hi) return static_cast<int>(o);
+  }
+}
+}  // namespace
+
+bsm_status make_pattern(uint64_t seed, int n, int S, double sigma, int8_t *out) {
+  if (!out) return fail(BSM_EINVAL, "pattern output is NULL");
+  if (n < 1 || n > kMaxBits) return fail(BSM_EINVAL, "n %d out of [1, %d]", n, kMaxBits);
+  if (S < 2 || S > kMaxWindow) return fail(BSM_EINVAL, "window %d out of [2, %d]", S, kMaxWindow);
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(BSM_EINVAL, "sigma must be > 0");
+  const int lo = -(S / 2), hi = (S - 1) / 2;
+  SplitMix64 g{seed};
+  for (int i = 0; i < n; ++i) {
+    int p[2], q[2];
+    p[0] = offset_in_window(g, sigma, lo, hi);
+    p[1] = offset_in_window(g, sigma, lo, hi);
+    do {
+      q[0] = offset_in_window(g, sigma, lo, hi);
+      q[1] = offset_in_window(g, sigma, lo, hi);
+    } while (q[0] == p[0] && q[1] == p[1]);
+    int8_t *row = out + 4 * i;
+    row[0] = (int8_t)p[0];
+    row[1] = (int8_t)p[1];
+    row[2] = (int8_t)q[0];
+    row[3] = (int8_t)q[1];
+  }
+  return BSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Integer CIELAB tables.  sRGB decoding (IEC 61966-2-1), the sRGB->XYZ matrix
+// of the same standard with each row divided by the D65 white (its row sum)
+// and rounded to Q14 so that each row sums to 16384 exactly (greys map to
+// a = b = 0), and the CIE companding function f on a 16-bit grid.  Doubles
+// are rounded half away from zero.
+// ---------------------------------------------------------------------------
+void build_color_tables(ColorTables *t) {
+  for (int c = 0; c < 256; ++c) {
+    double x = c / 255.0;
+    double lin = x <= 0.04045 ? x / 12.92 : std::pow((x + 0.055) / 1.055, 2.4);
+    t->lin[c] = (uint16_t)std::lround(65535.0 * lin);
+  }
+  static const double M[3][3] = {{0.4124, 0.3576, 0.1805},
+                                 {0.2126, 0.7152, 0.0722},
+                                 {0.0193, 0.1192, 0.9505}};
+  for (int r = 0; r < 3; ++r) {
+    const double white = M[r][0] + M[r][1] + M[r][2];
+    int32_t *row = t->mq + 3 * r;
+    int largest = 0;
+    for (int c = 0; c < 3; ++c) {
+      row[c] = (int32_t)std::lround(16384.0 * M[r][c] / white);
+      if (row[c] > row[largest]) largest = c;
+    }
+    row[largest] += 16384 - (row[0] + row[1] + row[2]);
+  }
+  t->f.resize(65536);
+  const double e = 6.0 / 29.0;
+  for (int i = 0; i < 65536; ++i) {
+    double x = i / 65535.0;
+    double f = x > e * e * e ? std::cbrt(x) : x / (3.0 * e * e) + 4.0 / 29.0;
+    t->f[i] = (uint16_t)std::lround(65535.0 * f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+Scratch::~Scratch() {
+  if (ev_) {
+    if (used_) (void)hipEventSynchronize(ev_);
+    (void)hipEventDestroy(ev_);
+  }
+  if (ptr_) (void)hipFree(ptr_);
+}
+
+void *Scratch::acquire(size_t bytes, hipStream_t s, hipError_t *err) {
+  *err = hipSuccess;
+  if (!ev_) {
+    *err = hipEventCreateWithFlags(&ev_, hipEventDisableTiming);
+    if (*err != hipSuccess) return nullptr;
+  }
+  if (bytes > cap_) {
+    if (used_) {
+      *err = hipEventSynchronize(ev_);
+      if (*err != hipSuccess) return nullptr;
+    }
+    if (ptr_) (void)hipFree(ptr_);
+    ptr_ = nullptr;
+    cap_ = 0;
+    *err = hipMalloc(&ptr_, bytes);
+    if (*err != hipSuccess) {
+      ptr_ = nullptr;
+      return nullptr;
+    }
+    cap_ = bytes;
+  } else if (used_ && last_ != s) {
+    *err = hipStreamWaitEvent(s, ev_, 0);
+    if (*err != hipSuccess) return nullptr;
+  }
+  return ptr_;
+}
+
+hipError_t Scratch::release(hipStream_t s) {
+  used_ = true;
+  last_ = s;
+  return hipEventRecord(ev_, s);
+}
+
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H) {
+  size_t px = (size_t)W * H;
+  size_t plane = round_up(px * 4, 256);
+  size_t desc = round_up(px * ctx->nw * 8, 256);
+  return plane + 3 * desc;
+}
+
+// The whole hot path of one pair on stream s; `scratch` holds
+// match_scratch_bytes(W, H).
+bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
+                           int W, int H, int stride, int dmax, int32_t *disp,
+                           int16_t *cost, void *scratch, hipStream_t s) {
+  size_t px = (size_t)W * H;
+  char *base = static_cast<char *>(scratch);
+  uint32_t *packed = reinterpret_cast<uint32_t *>(base);
+  size_t desc_bytes = round_up(px * ctx->nw * 8, 256);
+  uint64_t *descL = reinterpret_cast<uint64_t *>(base + round_up(px * 4, 256));
+  uint64_t *maskL = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(descL) + desc_bytes);
+  uint64_t *descR = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(maskL) + desc_bytes);
+  const bool m = ctx->use_mask != 0;
+  hipError_t e;
+  if ((e = launch_color(left, W, H, stride, packed, m, ctx->dt, s)) != hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass (left)");
+  if ((e = launch_describe(packed, W, H, ctx->dt, descL, m ? maskL : nullptr, s)) != hipSuccess)
+    return device_fail(ctx, e, "describe (left)");
+  if ((e = launch_color(right, W, H, stride, packed, 0, ctx->dt, s)) != hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass (right)");
+  if ((e = launch_describe(packed, W, H, ctx->dt, descR, nullptr, s)) != hipSuccess)
+    return device_fail(ctx, e, "describe (right)");
+  if ((e = launch_cost_wta(descL, m ? maskL : nullptr, descR, W, H, ctx->nw, dmax, disp, cost, s)) !=
+      hipSuccess)
+    return device_fail(ctx, e, "cost + WTA");
+  return BSM_OK;
+}
+
+}  // namespace bsm
+
+using namespace bsm;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *bsm_last_error(void) { return g_last_error.c_str(); }
+
+bsm_status bsm_make_pattern(uint64_t seed, int32_t n, int32_t S, double sigma, int8_t *out) {
+  clear_error();
+  return make_pattern(seed, n, S, sigma, out);
+}
+
+bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
+  clear_error();
+  if (!p || !out) return fail(BSM_EINVAL, "params and out must not be NULL");
+  *out = nullptr;
+  if (p->n_bits < 64 || p->n_bits > kMaxBits || p->n_bits % 64)
+    return fail(BSM_EINVAL, "n_bits %d must be a multiple of 64 in [64, %d]", p->n_bits, kMaxBits);
+  if (p->window < 2 || p->window > kMaxWindow)
+    return fail(BSM_EINVAL, "window %d out of [2, %d]", p->window, kMaxWindow);
+  if (!std::isfinite(p->sigma)) return fail(BSM_EINVAL, "sigma is not finite");
+  const int k = p->mask_rank == 0 ? p->n_bits / 4 : p->mask_rank;
+  if (k < 1 || k > p->n_bits)
+    return fail(BSM_EINVAL, "mask_rank %d out of [1, n=%d]", p->mask_rank, p->n_bits);
+  if (p->use_mask != 0 && p->use_mask != 1) return fail(BSM_EINVAL, "use_mask must be 0 or 1");
+  std::unique_ptr<bsm_ctx> ctx(new bsm_ctx);
+  ctx->device = hip_device;
+  ctx->n = p->n_bits;
+  ctx->nw = p->n_bits / 64;
+  ctx->S = p->window;
+  ctx->k = k;
+  ctx->use_mask = p->use_mask;
+  ctx->sigma = p->sigma > 0 ? p->sigma : 4.0 * p->window / 26.0;
+  ctx->seed = p->seed;
+  ctx->pattern.resize(4 * (size_t)ctx->n);
+  const int lo = -(ctx->S / 2), hi = (ctx->S - 1) / 2;
+  if (p->pattern) {
+    for (int i = 0; i < 4 * ctx->n; ++i) {
+      int o = p->pattern[i];
+      if (o < lo || o > hi)
+        return fail(BSM_EINVAL, "pattern entry %d (pair %d) = %d outside [%d, %d]", i, i / 4 + 1, o,
+                    lo, hi);
+      ctx->pattern[i] = p->pattern[i];
+    }
+  } else {
+    bsm_status st = make_pattern(ctx->seed, ctx->n, ctx->S, ctx->sigma, ctx->pattern.data());
+    if (st != BSM_OK) return st;
+  }
+  int radius = 0;
+  for (int8_t o : ctx->pattern) radius = std::max(radius, std::abs((int)o));
+  ctx->radius = radius;
+  build_color_tables(&ctx->tables);
+
+  // host-side validation is complete; from here on the device is touched
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(BSM_EDEVICE, "no HIP device available");
+  if (hip_device < 0 || hip_device >= ndev)
+    return fail(BSM_EINVAL, "device %d out of [0, %d)", hip_device, ndev);
+
+  DeviceGuard g(hip_device);
+  if (g.err() != hipSuccess) return device_fail(nullptr, g.err(), "hipSetDevice");
+  hipError_t e;
+  if ((e = hipMalloc(&ctx->d_pattern, ctx->pattern.size())) != hipSuccess ||
+      (e = hipMalloc(&ctx->d_lin, 256 * sizeof(uint16_t))) != hipSuccess ||
+      (e = hipMalloc(&ctx->d_f, 65536 * sizeof(uint16_t))) != hipSuccess) {
+    bsm_destroy(ctx.release());
+    return device_fail(nullptr, e, "allocating context tables");
+  }
+  if ((e = hipMemcpy(ctx->d_pattern, ctx->pattern.data(), ctx->pattern.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->d_lin, ctx->tables.lin, 256 * sizeof(uint16_t), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(ctx->d_f, ctx->tables.f.data(), 65536 * sizeof(uint16_t),
+                     hipMemcpyHostToDevice)) != hipSuccess) {
+    bsm_destroy(ctx.release());
+    return device_fail(nullptr, e, "uploading context tables");
+  }
+  DeviceTables &dt = ctx->dt;
+  dt.pattern = ctx->d_pattern;
+  dt.lin = ctx->d_lin;
+  dt.f = ctx->d_f;
+  std::memcpy(dt.mq.m, ctx->tables.mq, sizeof dt.mq.m);
+  dt.n = ctx->n;
+  dt.nw = ctx->nw;
+  dt.k = ctx->k;
+  dt.radius = ctx->radius;
+  *out = ctx.release();
+  return BSM_OK;
+}
+
+void bsm_destroy(bsm_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->server) server_stop(ctx->server);
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->batch) batch_state_free(ctx->batch);
+  if (ctx->d_pattern) (void)hipFree(ctx->d_pattern);
+  if (ctx->d_lin) (void)hipFree(ctx->d_lin);
+  if (ctx->d_f) (void)hipFree(ctx->d_f);
+  delete ctx;  // scratch buffers are released with the device still current
+}
+
+bsm_status bsm_pattern(const bsm_ctx *ctx, int8_t *out) {
+  clear_error();
+  if (!ctx || !out) return fail(BSM_EINVAL, "context and out must not be NULL");
+  std::memcpy(out, ctx->pattern.data(), ctx->pattern.size());
+  return BSM_OK;
+}
+
+size_t bsm_footprint(const bsm_ctx *ctx, int32_t W, int32_t H, int32_t dmax, int32_t want_cost) {
+  clear_error();
+  if (!ctx || W < 1 || H < 1 || dmax < 1 || dmax > W) return 0;
+  size_t bytes = match_scratch_bytes(ctx, W, H);
+  if (want_cost) bytes += (size_t)dmax * W * H * sizeof(int16_t);
+  return bytes;
+}
+
+bsm_status bsm_color(bsm_ctx *ctx, const uint8_t *img, int32_t W, int32_t H, int32_t stride,
+                     uint32_t *packed, int32_t want_lab, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_image(img, W, H, stride)) != BSM_OK) return st;
+  if (!packed || (reinterpret_cast<uintptr_t>(packed) & 3u))
+    return fail(BSM_EINVAL, "packed output must be a 4-byte aligned device pointer");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipError_t e = launch_color(img, W, H, stride, packed, want_lab ? 1 : 0, ctx->dt,
+                              static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? BSM_OK : device_fail(ctx, e, "colour pre-pass");
+}
+
+bsm_status bsm_describe(bsm_ctx *ctx, const uint8_t *img, int32_t W, int32_t H, int32_t stride,
+                        uint64_t *desc, uint64_t *mask, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_image(img, W, H, stride)) != BSM_OK) return st;
+  if (!desc || !aligned8(desc)) return fail(BSM_EINVAL, "desc must be an 8-byte aligned device pointer");
+  if (mask && !aligned8(mask)) return fail(BSM_EINVAL, "mask must be 8-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  void *buf = ctx->describe_scratch.acquire((size_t)W * H * 4, s, &e);
+  if (!buf) return device_fail(ctx, e, "describe scratch");
+  if ((e = launch_color(img, W, H, stride, static_cast<uint32_t *>(buf), mask != nullptr, ctx->dt, s)) !=
+      hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass");
+  if ((e = launch_describe(static_cast<uint32_t *>(buf), W, H, ctx->dt, desc, mask, s)) != hipSuccess)
+    return device_fail(ctx, e, "describe");
+  if ((e = ctx->describe_scratch.release(s)) != hipSuccess)
+    return device_fail(ctx, e, "describe scratch event");
+  return BSM_OK;
+}
+
+bsm_status bsm_describe_packed(bsm_ctx *ctx, const uint32_t *packed, int32_t W, int32_t H,
+                               uint64_t *desc, uint64_t *mask, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_image(packed, W, H, 3 * W)) != BSM_OK) return st;
+  if (reinterpret_cast<uintptr_t>(packed) & 3u) return fail(BSM_EINVAL, "packed must be 4-byte aligned");
+  if (!desc || !aligned8(desc)) return fail(BSM_EINVAL, "desc must be an 8-byte aligned device pointer");
+  if (mask && !aligned8(mask)) return fail(BSM_EINVAL, "mask must be 8-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipError_t e = launch_describe(packed, W, H, ctx->dt, desc, mask, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? BSM_OK : device_fail(ctx, e, "describe");
+}
+
+bsm_status bsm_cost_wta(bsm_ctx *ctx, const uint64_t *descL, const uint64_t *maskL,
+                        const uint64_t *descR, int32_t W, int32_t H, int32_t dmax, int32_t *disp,
+                        int16_t *cost, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide)
+    return fail(BSM_EINVAL, "image size %dx%d out of range", W, H);
+  if ((st = validate_dmax(W, dmax)) != BSM_OK) return st;
+  if (!descL || !descR || !disp) return fail(BSM_EINVAL, "descL, descR and disp must not be NULL");
+  if (!aligned8(descL) || !aligned8(descR) || (maskL && !aligned8(maskL)) ||
+      (reinterpret_cast<uintptr_t>(disp) & 3u) || (reinterpret_cast<uintptr_t>(cost) & 3u))
+    return fail(BSM_EINVAL, "misaligned device pointer");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipError_t e = launch_cost_wta(descL, maskL, descR, W, H, ctx->nw, dmax, disp, cost,
+                                 static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? BSM_OK : device_fail(ctx, e, "cost + WTA");
+}
+
+bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, int32_t W, int32_t H,
+                     int32_t stride, int32_t dmax, int32_t *disp, int16_t *cost, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_image(left, W, H, stride)) != BSM_OK) return st;
+  if ((st = validate_image(right, W, H, stride)) != BSM_OK) return st;
+  if ((st = validate_dmax(W, dmax)) != BSM_OK) return st;
+  if (!disp || (reinterpret_cast<uintptr_t>(disp) & 3u) || (reinterpret_cast<uintptr_t>(cost) & 3u))
+    return fail(BSM_EINVAL, "disp must be a 4-byte aligned device pointer (cost too)");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  void *buf = ctx->match_scratch.acquire(match_scratch_bytes(ctx, W, H), s, &e);
+  if (!buf) return device_fail(ctx, e, "match scratch");
+  st = match_on_stream(ctx, left, right, W, H, stride, dmax, disp, cost, buf, s);
+  if (st != BSM_OK) return st;
+  if ((e = ctx->match_scratch.release(s)) != hipSuccess)
+    return device_fail(ctx, e, "match scratch event");
+  return BSM_OK;
+}
+
+}  // extern "C"

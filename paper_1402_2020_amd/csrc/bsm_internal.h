@@ -1,0 +1,135 @@
+// Internal declarations of the BSM library (host runtime <-> kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bsm.h"
+
+namespace bsm {
+
+// Upper limits of the device code.
+constexpr int kMaxBits = 4096;
+constexpr int kMaxWords = kMaxBits / 64;
+constexpr int kMaxWindow = 63;
+constexpr int kInvalidCost = 32767;
+constexpr int kMaxSide = 32768;  // largest W or H (grid y limit)
+
+// Integer colour tables (built on the host, used by the colour kernel).
+struct ColorTables {
+  uint16_t lin[256];      // sRGB decode, 65535 * s(c / 255)
+  int32_t mq[9];          // Q14 rows of the white-normalised sRGB->XYZ matrix
+  std::vector<uint16_t> f;  // 65536 entries, 65535 * f(t / 65535)
+};
+
+void build_color_tables(ColorTables *t);
+bsm_status make_pattern(uint64_t seed, int n, int S, double sigma, int8_t *out);
+
+// Small matrix passed to the colour kernel by value.
+struct Mq {
+  int32_t m[9];
+};
+
+// Device-side view of the constant data of a context.
+struct DeviceTables {
+  const int8_t *pattern;  // [n][4]
+  const uint16_t *lin;    // [256]
+  const uint16_t *f;      // [65536]
+  Mq mq;
+  int n, nw, k, radius;
+};
+
+// ---- kernel launchers (bsm_kernels.hip) -----------------------------------
+hipError_t launch_color(const uint8_t *img, int W, int H, int stride,
+                        uint32_t *packed, int want_lab, const DeviceTables &t,
+                        hipStream_t s);
+hipError_t launch_describe(const uint32_t *packed, int W, int H,
+                           const DeviceTables &t, uint64_t *desc,
+                           uint64_t *mask, hipStream_t s);
+hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL,
+                           const uint64_t *descR, int W, int H, int nw,
+                           int dmax, int32_t *disp, int16_t *cost,
+                           hipStream_t s);
+// Bytes of LDS the describe kernel needs for a pattern radius.
+size_t describe_lds_bytes(int radius);
+
+// ---- batch (bsm_batch.hip) --------------------------------------------------
+struct BatchState;
+void batch_state_free(BatchState *b);
+
+// ---- device scratch with stream-ordered reuse ---------------------------
+// A growable device buffer.  Every use is recorded with an event; a use on
+// another stream first waits for that event, and growing waits for it on the
+// host, so reuse never races with earlier work.
+class Scratch {
+ public:
+  ~Scratch();
+  // Returns a buffer of at least `bytes` usable on stream s (nullptr on
+  // failure; *err holds the HIP error).
+  void *acquire(size_t bytes, hipStream_t s, hipError_t *err);
+  // Records that the buffer was last used on stream s.
+  hipError_t release(hipStream_t s);
+  size_t capacity() const { return cap_; }
+
+ private:
+  void *ptr_ = nullptr;
+  size_t cap_ = 0;
+  hipEvent_t ev_ = nullptr;
+  bool used_ = false;
+  hipStream_t last_ = nullptr;
+};
+
+struct Server;
+void server_stop(Server *s);
+
+}  // namespace bsm
+
+struct bsm_ctx {
+  int device = 0;
+  int n = 0, nw = 0, S = 0, k = 0, use_mask = 1, radius = 0;
+  double sigma = 0;
+  uint64_t seed = 0;
+  std::vector<int8_t> pattern;
+  bsm::ColorTables tables;
+  // device copies
+  int8_t *d_pattern = nullptr;
+  uint16_t *d_lin = nullptr;
+  uint16_t *d_f = nullptr;
+  bsm::DeviceTables dt{};
+  bsm::Scratch describe_scratch;  // packed colour plane of bsm_describe
+  bsm::Scratch match_scratch;     // planes + descriptors of bsm_match
+  bool dead = false;
+  std::string dead_reason;
+  bsm::BatchState *batch = nullptr;
+  bsm::Server *server = nullptr;
+  std::mutex server_mu;  // guards lazy creation of `server`
+};
+
+namespace bsm {
+// Error plumbing (bsm_host.cpp).
+bsm_status fail(bsm_status st, const char *fmt, ...);
+bsm_status device_fail(bsm_ctx *ctx, hipError_t e, const char *what);
+bsm_status check_alive(bsm_ctx *ctx);
+void clear_error();
+// Validation shared by the entry points.
+bsm_status validate_image(const void *img, int W, int H, int stride);
+bsm_status validate_dmax(int W, int dmax);
+bool aligned8(const void *p);
+size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H);
+bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left,
+                           const uint8_t *right, int W, int H, int stride,
+                           int dmax, int32_t *disp, int16_t *cost,
+                           void *scratch, hipStream_t s);
+double now_seconds();
+}  // namespace bsm
