@@ -39,8 +39,9 @@
  *            tensor's data_ptr()); "host" = ordinary CPU memory.  Device
  *            calls take a HIP stream (hipStream_t, NULL = default stream),
  *            are stream-ordered and return once the work is enqueued.
- *            Device buffers must be 8-byte aligned (desc/mask/disp/cost) and
- *            must not overlap.  The caller owns every buffer it passes.
+ *            desc/mask buffers must be 16-byte aligned, disp/cost/packed
+ *            4-byte aligned; buffers must not overlap.  The caller owns
+ *            every buffer it passes.
  * Errors     Every call returns a status and never aborts.  Arguments are
  *            validated before any device work (BSM_EINVAL).  A failed HIP
  *            call returns BSM_EDEVICE and marks the context dead: every

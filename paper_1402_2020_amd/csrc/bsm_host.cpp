@@ -47,6 +47,7 @@ bsm_status check_alive(bsm_ctx *ctx) {
 }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 bsm_status validate_image(const void *img, int W, int H, int stride) {
   if (!img) return fail(BSM_EINVAL, "image pointer is NULL");
@@ -182,6 +183,38 @@ void build_color_tables(ColorTables *t) {
     double f = x > e * e * e ? std::cbrt(x) : x / (3.0 * e * e) + 4.0 / 29.0;
     t->f[i] = (uint16_t)std::lround(65535.0 * f);
   }
+}
+
+// ---------------------------------------------------------------------------
+// LDS pitch of the descriptor+mask tile.  In that kernel the 64 lanes of a
+// wave gather the samples of 64 pairs at once, at LDS word offsets
+// py * pitch + px from the same centre; LDS serves 32 lanes per cycle and a
+// half-wave takes as many cycles as its most loaded bank (32 banks of 4
+// bytes).  The offsets are random, but the pitch changes how they fall into
+// banks, so try the pitches [cols, cols + 32) and keep the one with the
+// fewest cycles summed over all words and both samples.
+// ---------------------------------------------------------------------------
+int choose_left_pitch(const int8_t *pattern, int n, int cols) {
+  int best_pitch = cols, best_cycles = -1;
+  for (int pitch = cols; pitch < cols + 32; ++pitch) {
+    int cycles = 0;
+    for (int word = 0; word < n / 64; ++word)
+      for (int sample = 0; sample < 2; ++sample)
+        for (int half = 0; half < 2; ++half) {
+          int load[32] = {0}, worst = 0;
+          for (int l = 0; l < 32; ++l) {
+            const int8_t *o = pattern + 4 * (64 * word + 32 * half + l) + 2 * sample;
+            const int bank = ((o[1] * pitch + o[0]) % 32 + 32) % 32;
+            worst = std::max(worst, ++load[bank]);
+          }
+          cycles += worst;
+        }
+    if (best_cycles < 0 || cycles < best_cycles) {
+      best_cycles = cycles;
+      best_pitch = pitch;
+    }
+  }
+  return best_pitch;
 }
 
 // ---------------------------------------------------------------------------
@@ -327,12 +360,23 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
   if (hip_device < 0 || hip_device >= ndev)
     return fail(BSM_EINVAL, "device %d out of [0, %d)", hip_device, ndev);
 
+  // LDS layouts of the describe kernels: the pitch of the descriptor+mask
+  // tile is chosen for this pattern; the intensity tile needs no padding.
+  const int left_pitch = choose_left_pitch(ctx->pattern.data(), ctx->n, describe_left_cols(radius));
+  const int right_pitch = describe_right_cols(radius);
+  std::vector<int2> right_offs(ctx->n);
+  for (int i = 0; i < ctx->n; ++i) {
+    const int8_t *o = &ctx->pattern[4 * i];
+    right_offs[i] = make_int2(o[1] * right_pitch + o[0], o[3] * right_pitch + o[2]);
+  }
+
   DeviceGuard g(hip_device);
   if (g.err() != hipSuccess) return device_fail(nullptr, g.err(), "hipSetDevice");
   hipError_t e;
   if ((e = hipMalloc(&ctx->d_pattern, ctx->pattern.size())) != hipSuccess ||
       (e = hipMalloc(&ctx->d_lin, 256 * sizeof(uint16_t))) != hipSuccess ||
-      (e = hipMalloc(&ctx->d_f, 65536 * sizeof(uint16_t))) != hipSuccess) {
+      (e = hipMalloc(&ctx->d_f, 65536 * sizeof(uint16_t))) != hipSuccess ||
+      (e = hipMalloc(&ctx->d_right_offs, right_offs.size() * sizeof(int2))) != hipSuccess) {
     bsm_destroy(ctx.release());
     return device_fail(nullptr, e, "allocating context tables");
   }
@@ -341,6 +385,8 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
       (e = hipMemcpy(ctx->d_lin, ctx->tables.lin, 256 * sizeof(uint16_t), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemcpy(ctx->d_f, ctx->tables.f.data(), 65536 * sizeof(uint16_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->d_right_offs, right_offs.data(), right_offs.size() * sizeof(int2),
                      hipMemcpyHostToDevice)) != hipSuccess) {
     bsm_destroy(ctx.release());
     return device_fail(nullptr, e, "uploading context tables");
@@ -349,6 +395,9 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
   dt.pattern = ctx->d_pattern;
   dt.lin = ctx->d_lin;
   dt.f = ctx->d_f;
+  dt.right_offs = ctx->d_right_offs;
+  dt.left_pitch = left_pitch;
+  dt.right_pitch = right_pitch;
   std::memcpy(dt.mq.m, ctx->tables.mq, sizeof dt.mq.m);
   dt.n = ctx->n;
   dt.nw = ctx->nw;
@@ -367,6 +416,7 @@ void bsm_destroy(bsm_ctx *ctx) {
   if (ctx->d_pattern) (void)hipFree(ctx->d_pattern);
   if (ctx->d_lin) (void)hipFree(ctx->d_lin);
   if (ctx->d_f) (void)hipFree(ctx->d_f);
+  if (ctx->d_right_offs) (void)hipFree(ctx->d_right_offs);
   delete ctx;  // scratch buffers are released with the device still current
 }
 
@@ -406,8 +456,8 @@ bsm_status bsm_describe(bsm_ctx *ctx, const uint8_t *img, int32_t W, int32_t H, 
   bsm_status st;
   if ((st = check_alive(ctx)) != BSM_OK) return st;
   if ((st = validate_image(img, W, H, stride)) != BSM_OK) return st;
-  if (!desc || !aligned8(desc)) return fail(BSM_EINVAL, "desc must be an 8-byte aligned device pointer");
-  if (mask && !aligned8(mask)) return fail(BSM_EINVAL, "mask must be 8-byte aligned");
+  if (!desc || !aligned16(desc)) return fail(BSM_EINVAL, "desc must be a 16-byte aligned device pointer");
+  if (mask && !aligned16(mask)) return fail(BSM_EINVAL, "mask must be 16-byte aligned");
   DeviceGuard g(ctx->device);
   if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -431,8 +481,8 @@ bsm_status bsm_describe_packed(bsm_ctx *ctx, const uint32_t *packed, int32_t W, 
   if ((st = check_alive(ctx)) != BSM_OK) return st;
   if ((st = validate_image(packed, W, H, 3 * W)) != BSM_OK) return st;
   if (reinterpret_cast<uintptr_t>(packed) & 3u) return fail(BSM_EINVAL, "packed must be 4-byte aligned");
-  if (!desc || !aligned8(desc)) return fail(BSM_EINVAL, "desc must be an 8-byte aligned device pointer");
-  if (mask && !aligned8(mask)) return fail(BSM_EINVAL, "mask must be 8-byte aligned");
+  if (!desc || !aligned16(desc)) return fail(BSM_EINVAL, "desc must be a 16-byte aligned device pointer");
+  if (mask && !aligned16(mask)) return fail(BSM_EINVAL, "mask must be 16-byte aligned");
   DeviceGuard g(ctx->device);
   if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
   hipError_t e = launch_describe(packed, W, H, ctx->dt, desc, mask, static_cast<hipStream_t>(hip_stream));
@@ -449,7 +499,7 @@ bsm_status bsm_cost_wta(bsm_ctx *ctx, const uint64_t *descL, const uint64_t *mas
     return fail(BSM_EINVAL, "image size %dx%d out of range", W, H);
   if ((st = validate_dmax(W, dmax)) != BSM_OK) return st;
   if (!descL || !descR || !disp) return fail(BSM_EINVAL, "descL, descR and disp must not be NULL");
-  if (!aligned8(descL) || !aligned8(descR) || (maskL && !aligned8(maskL)) ||
+  if (!aligned16(descL) || !aligned16(descR) || (maskL && !aligned16(maskL)) ||
       (reinterpret_cast<uintptr_t>(disp) & 3u) || (reinterpret_cast<uintptr_t>(cost) & 3u))
     return fail(BSM_EINVAL, "misaligned device pointer");
   DeviceGuard g(ctx->device);

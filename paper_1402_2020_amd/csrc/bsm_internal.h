@@ -43,12 +43,22 @@ struct Mq {
 
 // Device-side view of the constant data of a context.
 struct DeviceTables {
-  const int8_t *pattern;  // [n][4]
-  const uint16_t *lin;    // [256]
-  const uint16_t *f;      // [65536]
+  const int8_t *pattern;   // [n][4]
+  const uint16_t *lin;     // [256]
+  const uint16_t *f;       // [65536]
+  const int2 *right_offs;  // [n] (p, q) byte offsets in the intensity tile
   Mq mq;
   int n, nw, k, radius;
+  int left_pitch;   // LDS row pitch (words) of the descriptor+mask tile
+  int right_pitch;  // LDS row pitch (bytes) of the intensity tile
 };
+
+// Tile geometry of the describe kernels (bsm_kernels.hip).
+int describe_left_cols(int radius);   // tile width incl. halo, in pixels
+int describe_right_cols(int radius);
+// LDS pitch (pixels) for the descriptor+mask tile that minimises the bank
+// conflicts of the pattern's gathers (host search, bsm_host.cpp).
+int choose_left_pitch(const int8_t *pattern, int n, int cols);
 
 // ---- kernel launchers (bsm_kernels.hip) -----------------------------------
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride,
@@ -61,8 +71,6 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL,
                            const uint64_t *descR, int W, int H, int nw,
                            int dmax, int32_t *disp, int16_t *cost,
                            hipStream_t s);
-// Bytes of LDS the describe kernel needs for a pattern radius.
-size_t describe_lds_bytes(int radius);
 
 // ---- batch (bsm_batch.hip) --------------------------------------------------
 struct BatchState;
@@ -106,6 +114,7 @@ struct bsm_ctx {
   int8_t *d_pattern = nullptr;
   uint16_t *d_lin = nullptr;
   uint16_t *d_f = nullptr;
+  int2 *d_right_offs = nullptr;
   bsm::DeviceTables dt{};
   bsm::Scratch describe_scratch;  // packed colour plane of bsm_describe
   bsm::Scratch match_scratch;     // planes + descriptors of bsm_match
@@ -126,6 +135,7 @@ void clear_error();
 bsm_status validate_image(const void *img, int W, int H, int stride);
 bsm_status validate_dmax(int W, int dmax);
 bool aligned8(const void *p);
+bool aligned16(const void *p);
 size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H);
 bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left,
                            const uint8_t *right, int W, int H, int stride,

@@ -6,6 +6,8 @@
 //
 // Nothing on this path is a dense contraction, so there is no MFMA: the
 // kernels are bound by integer VALU issue (cost, descriptor) or HBM (colour).
+#include <type_traits>
+
 #include "bsm_internal.h"
 
 namespace bsm {
@@ -64,86 +66,241 @@ __global__ __launch_bounds__(256) void k_color(const uint8_t *__restrict__ img, 
 // weights in registers and the k-th smallest weight T is found by bisection
 // on [0, 765], each probe counting ballot(w <= t) words with a popcount.
 // ---------------------------------------------------------------------------
-constexpr int kDescTW = 32, kDescTH = 8, kDescThreads = 256;
+constexpr int kDescTW = 16, kDescTH = 8, kDescThreads = 256;
 
-template <int NWMAX, bool MASK>
+// v_writelane_b32 through the LLVM intrinsic (this clang has no builtin for
+// it), so that the compiler's hazard handling sees it: an SGPR written by a
+// VALU compare must not be read by v_writelane in the very next cycles.
+__device__ int writelane_i32(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// Puts the wave-uniform 64-bit value `bits` into lane J of (lo, hi).
+template <int J>
+__device__ __forceinline__ void put_word(uint64_t bits, uint32_t &lo, uint32_t &hi) {
+  lo = static_cast<uint32_t>(writelane_i32(static_cast<int>(static_cast<uint32_t>(bits)), J,
+                                           static_cast<int>(lo)));
+  hi = static_cast<uint32_t>(writelane_i32(static_cast<int>(static_cast<uint32_t>(bits >> 32)), J,
+                                           static_cast<int>(hi)));
+}
+
+// Applies f<J>() for J = 0 .. N-1 (compile-time lane indices).
+template <int N, int J = 0, typename F>
+__device__ __forceinline__ void for_words(F &&f) {
+  if constexpr (J < N) {
+    f(std::integral_constant<int, J>{});
+    for_words<N, J + 1>(f);
+  }
+}
+
+// One pixel of the descriptor (and mask).  ap/aq: LDS byte addresses of this
+// lane's samples for the group's first pixel; `shift` (bytes, compile-time
+// after unrolling) moves them to this pixel through the instruction's
+// immediate offset.  out: this pixel's words in desc / mask.
+template <int NW, bool MASK>
+__device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, const int *aq,
+                                               int centre_addr, int shift, int lane, int nw,
+                                               int k_eff, uint64_t *out_desc,
+                                               uint64_t *out_mask) {
+  uint32_t a[NW], b[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    a[j] = *reinterpret_cast<const uint32_t *>(lds + ap[j] + shift);
+    b[j] = *reinterpret_cast<const uint32_t *>(lds + aq[j] + shift);
+  }
+  uint32_t d_lo = 0, d_hi = 0;
+  for_words<NW>([&](auto J) {  // tau of Eq. 3
+    put_word<J.value>(__ballot((a[J.value] >> 24) > (b[J.value] >> 24)), d_lo, d_hi);
+  });
+  uint32_t m_lo = 0, m_hi = 0;
+  if (MASK) {
+    const uint32_t centre = *reinterpret_cast<const uint32_t *>(lds + centre_addr) & 0xffffffu;
+    uint32_t w[NW];
+    uint32_t wmax = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t sp = __builtin_amdgcn_sad_u8(a[j] & 0xffffffu, centre, 0u);
+      const uint32_t sq = __builtin_amdgcn_sad_u8(b[j] & 0xffffffu, centre, 0u);
+      w[j] = sp > sq ? sp : sq;  // Eq. 5
+      wmax = wmax > w[j] ? wmax : w[j];
+    }
+    // T is the smallest t with #{w <= t} >= k (the k-th smallest weight).
+    // It lies in [0, max w]; search [0, 2^b - 1] for the smallest such
+    // power-of-two range, then bisect.
+    int hi = 1023;
+    while (hi > 0 && __ballot(wmax > (uint32_t)(hi >> 1)) == 0) hi >>= 1;
+    int lo = 0;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      int count = 0;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) count += __popcll(__ballot(w[j] <= (uint32_t)mid));
+      if (count >= k_eff)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    for_words<NW>([&](auto J) {  // Eq. 6-7
+      put_word<J.value>(__ballot(w[J.value] <= (uint32_t)lo), m_lo, m_hi);
+    });
+  }
+  if (lane < nw) {
+    out_desc[lane] = (static_cast<uint64_t>(d_hi) << 32) | d_lo;
+    if (MASK) out_mask[lane] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
+  }
+}
+
+template <int NW, bool MASK>
 __global__ __launch_bounds__(kDescThreads) void k_describe(
     const uint32_t *__restrict__ packed, int W, int H, const int8_t *__restrict__ pattern, int nw,
     int radius, int pitch, int k, uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
   const int u0 = blockIdx.x * kDescTW, v0 = blockIdx.y * kDescTH;
   const int rows = kDescTH + 2 * radius, cols = kDescTW + 2 * radius;
-  for (int i = threadIdx.x; i < rows * cols; i += kDescThreads) {
-    const int ty = i / cols, tx = i - ty * cols;
-    const int gv = min(max(v0 - radius + ty, 0), H - 1);
-    const int gu = min(max(u0 - radius + tx, 0), W - 1);
-    tile[ty * pitch + tx] = packed[(size_t)gv * W + gu];
+  const int total = rows * cols;
+  // Stage the tile with kBatch independent loads in flight per thread.
+  constexpr int kBatch = 8;
+  for (int first = threadIdx.x; first < total; first += kDescThreads * kBatch) {
+    uint32_t staged[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int i = first + b * kDescThreads;
+      staged[b] = 0;
+      if (i < total) {
+        const int ty = i / cols, tx = i - ty * cols;
+        const int gv = min(max(v0 - radius + ty, 0), H - 1);
+        const int gu = min(max(u0 - radius + tx, 0), W - 1);
+        staged[b] = packed[(size_t)gv * W + gu];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int i = first + b * kDescThreads;
+      if (i < total) {
+        const int ty = i / cols, tx = i - ty * cols;
+        tile[ty * pitch + tx] = staged[b];
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // LDS offsets (relative to the centre) of this lane's pairs.
-  int offp[NWMAX], offq[NWMAX];
+  // Byte offsets in LDS, relative to the centre, of this lane's pair samples.
+  // Words past nw (NW is nw rounded up to a power of two) get offset 0: their
+  // "pairs" compare the centre with itself, so their weight is 0 and they
+  // only shift the rank of the threshold by 64 per padded word.
+  int offp[NW], offq[NW];
   const int32_t *pat32 = reinterpret_cast<const int32_t *>(pattern);
 #pragma unroll
-  for (int j = 0; j < NWMAX; ++j) {
+  for (int j = 0; j < NW; ++j) {
     offp[j] = offq[j] = 0;
     if (j < nw) {
       const int32_t e = pat32[64 * j + lane];
       const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
       const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
-      offp[j] = py * pitch + px;
-      offq[j] = qy * pitch + qx;
+      offp[j] = 4 * (py * pitch + px);
+      offq[j] = 4 * (qy * pitch + qx);
+    }
+  }
+  const int k_eff = k + 64 * (NW - nw);
+  __syncthreads();
+
+  const char *lds = reinterpret_cast<const char *>(tile);
+  constexpr int kRowsPerWave = kDescTH / (kDescThreads / 64);
+  constexpr int kGroup = 4;  // pixels whose LDS addresses share one base
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int ty = wave * kRowsPerWave + r, v = v0 + ty;
+    if (v >= H) break;  // uniform
+    for (int g = 0; g < kDescTW; g += kGroup) {
+      if (u0 + g >= W) break;  // uniform
+      const int c0 = 4 * ((ty + radius) * pitch + (g + radius));
+      int ap[NW], aq[NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        ap[j] = c0 + offp[j];
+        aq[j] = c0 + offq[j];
+      }
+#pragma unroll
+      for (int t = 0; t < kGroup; ++t) {
+        const int u = u0 + g + t;
+        if (u >= W) break;  // uniform
+        describe_pixel<NW, MASK>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, nw, k_eff,
+                                 desc + ((size_t)v * W + u) * nw,
+                                 MASK ? mask + ((size_t)v * W + u) * nw : nullptr);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2 (descriptor only, the non-reference view).  Here the lanes run over 64
+// consecutive pixels of a row and the point pairs are walked in a uniform
+// loop: for pair i all lanes read the intensity at the same offset from
+// their own pixel, i.e. 64 consecutive bytes of an LDS intensity tile, which
+// is free of bank conflicts.  The pair offsets (bytes in the tile) come from
+// a per-context table through scalar loads.  Each lane shifts its binary
+// tests into its own descriptor words, most significant pair first, so that
+// pair 64 j + 32 h + b ends at bit b of half h of word j.
+// ---------------------------------------------------------------------------
+constexpr int kRightTW = 64, kRightTH = 8, kRightThreads = 512;
+
+__global__ __launch_bounds__(kRightThreads) void k_describe_right(
+    const uint32_t *__restrict__ packed, int W, int H, const int2 *__restrict__ offs_global,
+    int nw, int radius, int pitch, uint64_t *__restrict__ desc) {
+  // LDS: the pair offsets (read back as wave-uniform broadcasts, so that the
+  // only outstanding operations in the pair loop are in-order LDS reads),
+  // then the intensity tile.
+  extern __shared__ int2 lds_offs[];
+  uint8_t *itile = reinterpret_cast<uint8_t *>(lds_offs + 64 * nw);
+  for (int i = threadIdx.x; i < 64 * nw; i += kRightThreads) lds_offs[i] = offs_global[i];
+  const int2 *offs = lds_offs;
+  const int u0 = blockIdx.x * kRightTW, v0 = blockIdx.y * kRightTH;
+  const int rows = kRightTH + 2 * radius, cols = kRightTW + 2 * radius;
+  const int total = rows * cols;
+  constexpr int kBatch = 8;
+  for (int first = threadIdx.x; first < total; first += kRightThreads * kBatch) {
+    uint32_t staged[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int i = first + b * kRightThreads;
+      staged[b] = 0;
+      if (i < total) {
+        const int ty = i / cols, tx = i - ty * cols;
+        const int gv = min(max(v0 - radius + ty, 0), H - 1);
+        const int gu = min(max(u0 - radius + tx, 0), W - 1);
+        staged[b] = packed[(size_t)gv * W + gu];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int i = first + b * kRightThreads;
+      if (i < total) {
+        const int ty = i / cols, tx = i - ty * cols;
+        itile[ty * pitch + tx] = static_cast<uint8_t>(staged[b] >> 24);
+      }
     }
   }
   __syncthreads();
-
-  constexpr int kPixPerWave = kDescTW * kDescTH / (kDescThreads / 64);
-  for (int p = 0; p < kPixPerWave; ++p) {
-    const int ty = wave * (kPixPerWave / kDescTW) + p / kDescTW, tx = p % kDescTW;
-    const int u = u0 + tx, v = v0 + ty;
-    if (u >= W || v >= H) continue;  // uniform across the wave
-    const int c = (ty + radius) * pitch + (tx + radius);
-    const uint32_t centre = tile[c] & 0xffffffu;
-    uint64_t out_desc = 0, out_mask = 0;
-    uint32_t w[NWMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kRowsPerWave = kRightTH / (kRightThreads / 64);
+  const int u = u0 + lane;
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int ty = wave * kRowsPerWave + r, v = v0 + ty;
+    if (v >= H) break;  // uniform
+    const uint8_t *centre = itile + (ty + radius) * pitch + (lane + radius);
+    uint64_t *out = desc + ((size_t)v * W + min(u, W - 1)) * nw;
+    for (int j = 0; j < nw; ++j) {
+      uint32_t half[2];
 #pragma unroll
-    for (int j = 0; j < NWMAX; ++j) {
-      w[j] = 0;
-      if (j < nw) {
-        const uint32_t a = tile[c + offp[j]], b = tile[c + offq[j]];
-        const uint64_t bits = __ballot((a >> 24) > (b >> 24));  // tau of Eq. 3
-        if (lane == j) out_desc = bits;
-        if (MASK) {
-          const uint32_t sp = __builtin_amdgcn_sad_u8(a & 0xffffffu, centre, 0u);
-          const uint32_t sq = __builtin_amdgcn_sad_u8(b & 0xffffffu, centre, 0u);
-          w[j] = sp > sq ? sp : sq;  // Eq. 5
+      for (int h = 0; h < 2; ++h) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int b = 31; b >= 0; --b) {
+          const int2 o = offs[64 * j + 32 * h + b];
+          // tau of Eq. 3: for bytes p, q the difference q - p has bit 31 set
+          // exactly when p > q; alignbit shifts that bit into acc.
+          const uint32_t diff = static_cast<uint32_t>(centre[o.y]) - centre[o.x];
+          acc = __builtin_amdgcn_alignbit(acc, diff, 31);
         }
+        half[h] = acc;
       }
-    }
-    if (MASK) {
-      // smallest t with #{w <= t} >= k, i.e. the k-th smallest weight
-      int lo = 0, hi = 3 * 255;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        int count = 0;
-#pragma unroll
-        for (int j = 0; j < NWMAX; ++j)
-          if (j < nw) count += __popcll(__ballot(w[j] <= (uint32_t)mid));
-        if (count >= k)
-          hi = mid;
-        else
-          lo = mid + 1;
-      }
-#pragma unroll
-      for (int j = 0; j < NWMAX; ++j)
-        if (j < nw) {
-          const uint64_t bits = __ballot(w[j] <= (uint32_t)lo);  // Eq. 6-7
-          if (lane == j) out_mask = bits;
-        }
-    }
-    const size_t base = ((size_t)v * W + u) * nw;
-    if (lane < nw) {
-      desc[base + lane] = out_desc;
-      if (MASK) mask[base + lane] = out_mask;
+      if (u < W) out[j] = (static_cast<uint64_t>(half[1]) << 32) | half[0];
     }
   }
 }
@@ -170,15 +327,166 @@ constexpr int kCostTX = 128;     // pixels per wave
 constexpr int kCostDC = 64;      // disparities per LDS window
 constexpr int kCostHP = 97;      // words per parity half (>= (127 + 64) / 2, odd)
 
+// c + popcount(x) as one v_bcnt_u32_b32.  Written out so that the compiler
+// keeps one accumulating chain instead of re-associating the sum into trees
+// of extra adds.
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t c) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(c));
+  return r;
+}
+
+// (a ^ b) & m in one v_bitop3_b32: the immediate is the truth table of the
+// function evaluated on the operand patterns 0xF0, 0xCC, 0xAA.
+constexpr unsigned kXorAnd = (0xF0 ^ 0xCC) & 0xAA;
+
+// popcount((bl ^ br) & m) over nwords 64-bit words, on 32-bit halves: one
+// v_bitop3_b32 and one accumulating v_bcnt_u32_b32 per half.
 __device__ __forceinline__ uint32_t masked_cost(const uint64_t *bl, const uint64_t *m,
                                                 const uint64_t *br, int nwords, bool use_mask) {
   uint32_t c = 0;
 #pragma unroll
   for (int j = 0; j < nwords; ++j) {
-    const uint64_t x = use_mask ? ((bl[j] ^ br[j]) & m[j]) : (bl[j] ^ br[j]);
-    c += __popcll(x);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t a = static_cast<uint32_t>(bl[j] >> (32 * h));
+      const uint32_t b = static_cast<uint32_t>(br[j] >> (32 * h));
+      const uint32_t x =
+          use_mask ? __builtin_amdgcn_bitop3_b32(a, b, static_cast<uint32_t>(m[j] >> (32 * h)),
+                                                 kXorAnd)
+                   : (a ^ b);
+      c = bcnt_acc(x, c);
+    }
   }
   return c;
+}
+
+// LDS window of right descriptors.  Elements are chunks of CW consecutive
+// words of one pixel (16 bytes when n >= 128); the layout is
+// [chunk jc][parity of pixel][pixel / 2][CW words], so at every step the 64
+// lanes (which read pixels of one parity, 2 apart) touch 64 consecutive
+// chunks, and the chunk index only moves a compile-time immediate offset.
+template <int NW>
+struct Window {
+  static constexpr int CW = NW >= 2 ? 2 : 1;  // words per chunk
+  static constexpr int CPP = NW / CW;          // chunks per pixel
+  // u64 index of (chunk jc, relative pixel rel)
+  __device__ static int index(int jc, int rel) {
+    return ((jc * 2 + (rel & 1)) * kCostHP + (rel >> 1)) * CW;
+  }
+};
+
+// Copies the right descriptors of pixels [r_lo, r_lo + P) (zeros outside the
+// image) into the LDS window.  Pixel r's words are contiguous in global
+// memory, so the wave reads coalesced chunks with up to kBatch loads in
+// flight per lane before writing them to LDS.
+template <int NW>
+__device__ __forceinline__ void stage_window(const uint64_t *__restrict__ rowR, int r_lo, int P,
+                                             int W, int lane, uint64_t *win) {
+  using Win = Window<NW>;
+  constexpr int kBatch = 8;
+  const int total = P * Win::CPP;
+  for (int first = lane; first < total; first += 64 * kBatch) {
+    uint64_t staged[kBatch][Win::CW];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int c = first + 64 * b;
+      const int rel = c / Win::CPP, jc = c % Win::CPP;
+      const int r = r_lo + rel;
+#pragma unroll
+      for (int w = 0; w < Win::CW; ++w) staged[b][w] = 0;
+      if (c < total && r >= 0 && r < W) {
+        if (Win::CW == 2) {
+          const ulonglong2 x =
+              *reinterpret_cast<const ulonglong2 *>(rowR + (size_t)r * NW + 2 * jc);
+          staged[b][0] = x.x;
+          staged[b][Win::CW - 1] = x.y;
+        } else {
+          staged[b][0] = rowR[(size_t)r * NW + jc];
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int c = first + 64 * b;
+      if (c < total) {
+        const int rel = c / Win::CPP, jc = c % Win::CPP;
+        uint64_t *dst = win + Win::index(jc, rel);
+        if (Win::CW == 2)
+          *reinterpret_cast<ulonglong2 *>(dst) = make_ulonglong2(staged[b][0], staged[b][Win::CW - 1]);
+        else
+          dst[0] = staged[b][0];
+      }
+    }
+  }
+}
+
+// Loads the NW words of relative pixel `rel` from the window.
+template <int NW>
+__device__ __forceinline__ void load_right(const uint64_t *win, int rel, uint64_t *out) {
+  using Win = Window<NW>;
+#pragma unroll
+  for (int jc = 0; jc < Win::CPP; ++jc) {
+    const uint64_t *src = win + Win::index(jc, rel);
+    if (Win::CW == 2) {
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2 *>(src);
+      out[2 * jc] = x.x;
+      out[2 * jc + Win::CW - 1] = x.y;
+    } else {
+      out[jc] = src[0];
+    }
+  }
+}
+
+// Per-lane state of the fused cost + WTA kernel.
+template <int NW>
+struct CostLane {
+  uint64_t bla[NW], ma[NW], blb[NW], mb[NW];
+  uint32_t best_a, best_b;
+  int a, b;
+  bool has_a, has_b;
+};
+
+// One disparity step d for the lane's pixels a and b: `cur` receives
+// B_R(a - d) (relative pixel 2 lane + e), `prev` holds B_R(b - d).
+template <int NW, bool MASK, bool VOL, bool EDGE>
+__device__ __forceinline__ void cost_step(const uint64_t *win, int lane, int e, int d,
+                                          CostLane<NW> &s, const uint64_t *prev, uint64_t *cur,
+                                          int16_t *__restrict__ cost, int H, int W, int v) {
+  load_right<NW>(win, 2 * lane + e, cur);
+  const uint32_t ca = masked_cost(s.bla, s.ma, cur, NW, MASK);
+  const uint32_t cb = masked_cost(s.blb, s.mb, prev, NW, MASK);
+  const bool va = !EDGE || s.a - d >= 0, vb = !EDGE || s.b - d >= 0;
+  const uint32_t ka = (ca << 16) | (uint32_t)d, kb = (cb << 16) | (uint32_t)d;
+  if (va) s.best_a = min(s.best_a, ka);
+  if (vb) s.best_b = min(s.best_b, kb);
+  if (VOL) {
+    const uint32_t sa = va ? ca : (uint32_t)kInvalidCost;
+    const uint32_t sb = vb ? cb : (uint32_t)kInvalidCost;
+    int16_t *plane = cost + ((size_t)d * H + v) * W;
+    if (s.has_b && ((((size_t)d * H + v) * W) & 1) == 0) {
+      *reinterpret_cast<uint32_t *>(plane + s.a) = sa | (sb << 16);
+    } else {
+      if (s.has_a) plane[s.a] = (int16_t)sa;
+      if (s.has_b) plane[s.b] = (int16_t)sb;
+    }
+  }
+}
+
+// All steps d in [dc0, dc1) of one window, two per iteration so that the two
+// register buffers swap roles without copies.
+template <int NW, bool MASK, bool VOL, bool EDGE>
+__device__ __forceinline__ void cost_chunk(const uint64_t *win, int lane, int dc0, int dc1,
+                                           CostLane<NW> &s, int16_t *__restrict__ cost, int H,
+                                           int W, int v) {
+  uint64_t x[NW], y[NW];
+  load_right<NW>(win, 2 * lane + (dc1 - dc0), x);  // B_R(b - dc0)
+  int d = dc0;
+  for (; d + 1 < dc1; d += 2) {
+    cost_step<NW, MASK, VOL, EDGE>(win, lane, dc1 - 1 - d, d, s, x, y, cost, H, W, v);
+    cost_step<NW, MASK, VOL, EDGE>(win, lane, dc1 - 2 - d, d + 1, s, y, x, cost, H, W, v);
+  }
+  if (d < dc1) cost_step<NW, MASK, VOL, EDGE>(win, lane, dc1 - 1 - d, d, s, x, y, cost, H, W, v);
 }
 
 template <int NW, bool MASK, bool VOL>
@@ -187,84 +495,50 @@ __global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict
                                                       const uint64_t *__restrict__ descR, int W,
                                                       int H, int dmax, int32_t *__restrict__ disp,
                                                       int16_t *__restrict__ cost) {
-  extern __shared__ uint64_t win[];  // [NW][2][kCostHP]
+  extern __shared__ uint64_t win[];
   const int lane = threadIdx.x;
   const int v = blockIdx.y;
   const int u0 = blockIdx.x * kCostTX;
-  const int a = u0 + 2 * lane, b = a + 1;
-  const bool has_a = a < W, has_b = b < W;
-
-  uint64_t bla[NW], blb[NW], ma[NW], mb[NW];
+  CostLane<NW> s;
+  s.a = u0 + 2 * lane;
+  s.b = s.a + 1;
+  s.has_a = s.a < W;
+  s.has_b = s.b < W;
   {
-    const uint64_t *pa = descL + ((size_t)v * W + (has_a ? a : 0)) * NW;
-    const uint64_t *pb = descL + ((size_t)v * W + (has_b ? b : 0)) * NW;
+    const uint64_t *pa = descL + ((size_t)v * W + (s.has_a ? s.a : 0)) * NW;
+    const uint64_t *pb = descL + ((size_t)v * W + (s.has_b ? s.b : 0)) * NW;
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
-      bla[j] = has_a ? pa[j] : 0;
-      blb[j] = has_b ? pb[j] : 0;
+      s.bla[j] = s.has_a ? pa[j] : 0;
+      s.blb[j] = s.has_b ? pb[j] : 0;
     }
     if (MASK) {
-      const uint64_t *qa = maskL + ((size_t)v * W + (has_a ? a : 0)) * NW;
-      const uint64_t *qb = maskL + ((size_t)v * W + (has_b ? b : 0)) * NW;
+      const uint64_t *qa = maskL + ((size_t)v * W + (s.has_a ? s.a : 0)) * NW;
+      const uint64_t *qb = maskL + ((size_t)v * W + (s.has_b ? s.b : 0)) * NW;
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        ma[j] = has_a ? qa[j] : 0;
-        mb[j] = has_b ? qb[j] : 0;
+        s.ma[j] = s.has_a ? qa[j] : 0;
+        s.mb[j] = s.has_b ? qb[j] : 0;
       }
     }
   }
+  s.best_a = s.best_b = 0xffffffffu;
   const uint64_t *rowR = descR + (size_t)v * W * NW;
-  uint32_t best_a = 0xffffffffu, best_b = 0xffffffffu;
 
   for (int dc0 = 0; dc0 < dmax; dc0 += kCostDC) {
     const int dc1 = min(dmax, dc0 + kCostDC);
-    const int r_lo = u0 - dc1 + 1;               // first right pixel of the window
-    const int P = kCostTX - 1 + (dc1 - dc0);     // window width
-    __syncthreads();                             // previous window fully consumed
-    for (int i = lane; i < P * NW; i += 64) {
-      const int rel = i / NW, j = i % NW;
-      const int r = r_lo + rel;
-      const uint64_t val = (r >= 0 && r < W) ? rowR[(size_t)r * NW + j] : 0;
-      win[(j * 2 + (rel & 1)) * kCostHP + (rel >> 1)] = val;
-    }
+    const int r_lo = u0 - dc1 + 1;            // first right pixel of the window
+    const int P = kCostTX - 1 + (dc1 - dc0);  // window width
+    __syncthreads();                          // previous window fully consumed
+    stage_window<NW>(rowR, r_lo, P, W, lane, win);
     __syncthreads();
-
-    // B_R(b - dc0): relative index 2l + (dc1 - dc0)
-    uint64_t prev[NW], cur[NW];
-    {
-      const int rel = 2 * lane + (dc1 - dc0);
-#pragma unroll
-      for (int j = 0; j < NW; ++j) prev[j] = win[(j * 2 + (rel & 1)) * kCostHP + (rel >> 1)];
-    }
-    const bool edge = u0 < dc1 - 1;  // some a - d < 0 inside this chunk
-    for (int d = dc0; d < dc1; ++d) {
-      const int e = dc1 - 1 - d;  // B_R(a - d): relative index 2l + e
-      const uint64_t *src = win + (e & 1) * kCostHP + lane + (e >> 1);
-#pragma unroll
-      for (int j = 0; j < NW; ++j) cur[j] = src[j * 2 * kCostHP];
-      const uint32_t ca = masked_cost(bla, ma, cur, NW, MASK);
-      const uint32_t cb = masked_cost(blb, mb, prev, NW, MASK);
-      const bool va = !edge || a - d >= 0, vb = !edge || b - d >= 0;
-      const uint32_t ka = (ca << 16) | (uint32_t)d, kb = (cb << 16) | (uint32_t)d;
-      if (va) best_a = min(best_a, ka);
-      if (vb) best_b = min(best_b, kb);
-      if (VOL) {
-        const uint32_t sa = va ? ca : (uint32_t)kInvalidCost;
-        const uint32_t sb = vb ? cb : (uint32_t)kInvalidCost;
-        int16_t *plane = cost + ((size_t)d * H + v) * W;
-        if (has_b && ((((size_t)d * H + v) * W) & 1) == 0) {
-          *reinterpret_cast<uint32_t *>(plane + a) = sa | (sb << 16);
-        } else {
-          if (has_a) plane[a] = (int16_t)sa;
-          if (has_b) plane[b] = (int16_t)sb;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NW; ++j) prev[j] = cur[j];
-    }
+    if (u0 < dc1 - 1)  // some a - d < 0 inside this chunk
+      cost_chunk<NW, MASK, VOL, true>(win, lane, dc0, dc1, s, cost, H, W, v);
+    else
+      cost_chunk<NW, MASK, VOL, false>(win, lane, dc0, dc1, s, cost, H, W, v);
   }
-  if (has_a) disp[(size_t)v * W + a] = (int32_t)(best_a & 0xffffu);
-  if (has_b) disp[(size_t)v * W + b] = (int32_t)(best_b & 0xffffu);
+  if (s.has_a) disp[(size_t)v * W + s.a] = (int32_t)(s.best_a & 0xffffu);
+  if (s.has_b) disp[(size_t)v * W + s.b] = (int32_t)(s.best_b & 0xffffu);
 }
 
 // ---------------------------------------------------------------------------
@@ -320,18 +594,13 @@ __global__ __launch_bounds__(64) void k_cost_wta_generic(const uint64_t *__restr
   if (lane < kGenTX && u0 + lane < W) disp[(size_t)v * W + u0 + lane] = (int32_t)(best & 0xffffu);
 }
 
-template <int NWMAX>
-hipError_t launch_describe_t(const uint32_t *packed, int W, int H, const DeviceTables &t,
-                             uint64_t *desc, uint64_t *mask, hipStream_t s) {
-  const int pitch = kDescTW + 2 * t.radius + 1;
-  const size_t lds = describe_lds_bytes(t.radius);
+template <int NW>
+hipError_t launch_describe_mask(const uint32_t *packed, int W, int H, const DeviceTables &t,
+                                uint64_t *desc, uint64_t *mask, hipStream_t s) {
+  const size_t lds = (size_t)(kDescTH + 2 * t.radius) * t.left_pitch * sizeof(uint32_t);
   dim3 grid((W + kDescTW - 1) / kDescTW, (H + kDescTH - 1) / kDescTH);
-  if (mask)
-    hipLaunchKernelGGL((k_describe<NWMAX, true>), grid, dim3(kDescThreads), lds, s, packed, W, H,
-                       t.pattern, t.nw, t.radius, pitch, t.k, desc, mask);
-  else
-    hipLaunchKernelGGL((k_describe<NWMAX, false>), grid, dim3(kDescThreads), lds, s, packed, W, H,
-                       t.pattern, t.nw, t.radius, pitch, t.k, desc, mask);
+  hipLaunchKernelGGL((k_describe<NW, true>), grid, dim3(kDescThreads), lds, s, packed, W, H,
+                     t.pattern, t.nw, t.radius, t.left_pitch, t.k, desc, mask);
   return hipGetLastError();
 }
 
@@ -356,10 +625,8 @@ hipError_t launch_cost_fast(const uint64_t *descL, const uint64_t *maskL, const 
 
 }  // namespace
 
-size_t describe_lds_bytes(int radius) {
-  const int pitch = kDescTW + 2 * radius + 1;
-  return (size_t)(kDescTH + 2 * radius) * pitch * sizeof(uint32_t);
-}
+int describe_left_cols(int radius) { return kDescTW + 2 * radius; }
+int describe_right_cols(int radius) { return kRightTW + 2 * radius; }
 
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride, uint32_t *packed,
                         int want_lab, const DeviceTables &t, hipStream_t s) {
@@ -371,13 +638,21 @@ hipError_t launch_color(const uint8_t *img, int W, int H, int stride, uint32_t *
 
 hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTables &t,
                            uint64_t *desc, uint64_t *mask, hipStream_t s) {
-  if (t.nw <= 1) return launch_describe_t<1>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 2) return launch_describe_t<2>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 4) return launch_describe_t<4>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 8) return launch_describe_t<8>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 16) return launch_describe_t<16>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 32) return launch_describe_t<32>(packed, W, H, t, desc, mask, s);
-  return launch_describe_t<64>(packed, W, H, t, desc, mask, s);
+  if (!mask) {
+    const size_t lds =
+        (size_t)t.n * sizeof(int2) + (size_t)(kRightTH + 2 * t.radius) * t.right_pitch;
+    dim3 grid((W + kRightTW - 1) / kRightTW, (H + kRightTH - 1) / kRightTH);
+    hipLaunchKernelGGL(k_describe_right, grid, dim3(kRightThreads), lds, s, packed, W, H,
+                       t.right_offs, t.nw, t.radius, t.right_pitch, desc);
+    return hipGetLastError();
+  }
+  if (t.nw <= 1) return launch_describe_mask<1>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 2) return launch_describe_mask<2>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 4) return launch_describe_mask<4>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 8) return launch_describe_mask<8>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 16) return launch_describe_mask<16>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 32) return launch_describe_mask<32>(packed, W, H, t, desc, mask, s);
+  return launch_describe_mask<64>(packed, W, H, t, desc, mask, s);
 }
 
 hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
