@@ -238,16 +238,27 @@ __global__ __launch_bounds__(kDescThreads) void k_describe(
 // tests into its own descriptor words, most significant pair first, so that
 // pair 64 j + 32 h + b ends at bit b of half h of word j.
 // ---------------------------------------------------------------------------
-constexpr int kRightTW = 64, kRightTH = 8, kRightThreads = 512;
+constexpr int kRightTW = 64, kRightTH = 4, kRightThreads = 256;
+constexpr int kRightGroup = 16;               // words staged per pixel at a time
+constexpr int kRightStagePitch = kRightGroup + 1;  // u64 per staged pixel (odd: fewer conflicts)
+
+// LDS bytes of k_describe_right: pair offsets, per-wave output staging, tile.
+__host__ __device__ constexpr size_t right_lds_bytes(int n, int radius, int pitch) {
+  return (size_t)n * sizeof(int2) +
+         (size_t)(kRightThreads / 64) * kRightTW * kRightStagePitch * sizeof(uint64_t) +
+         (size_t)(kRightTH + 2 * radius) * pitch;
+}
 
 __global__ __launch_bounds__(kRightThreads) void k_describe_right(
     const uint32_t *__restrict__ packed, int W, int H, const int2 *__restrict__ offs_global,
     int nw, int radius, int pitch, uint64_t *__restrict__ desc) {
   // LDS: the pair offsets (read back as wave-uniform broadcasts, so that the
   // only outstanding operations in the pair loop are in-order LDS reads),
-  // then the intensity tile.
+  // the output staging of each wave, then the intensity tile.
   extern __shared__ int2 lds_offs[];
-  uint8_t *itile = reinterpret_cast<uint8_t *>(lds_offs + 64 * nw);
+  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds_offs + 64 * nw);
+  uint8_t *itile = reinterpret_cast<uint8_t *>(
+      stage_all + (kRightThreads / 64) * kRightTW * kRightStagePitch);
   for (int i = threadIdx.x; i < 64 * nw; i += kRightThreads) lds_offs[i] = offs_global[i];
   const int2 *offs = lds_offs;
   const int u0 = blockIdx.x * kRightTW, v0 = blockIdx.y * kRightTH;
@@ -278,29 +289,52 @@ __global__ __launch_bounds__(kRightThreads) void k_describe_right(
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t *stage = stage_all + wave * kRightTW * kRightStagePitch;
   constexpr int kRowsPerWave = kRightTH / (kRightThreads / 64);
-  const int u = u0 + lane;
+  const int valid = min(kRightTW, W - u0);  // pixels of this tile inside the image
   for (int r = 0; r < kRowsPerWave; ++r) {
     const int ty = wave * kRowsPerWave + r, v = v0 + ty;
     if (v >= H) break;  // uniform
     const uint8_t *centre = itile + (ty + radius) * pitch + (lane + radius);
-    uint64_t *out = desc + ((size_t)v * W + min(u, W - 1)) * nw;
-    for (int j = 0; j < nw; ++j) {
-      uint32_t half[2];
+    uint64_t *row_out = desc + ((size_t)v * W + u0) * nw;
+    const int G = min(nw, kRightGroup);
+    for (int g0 = 0; g0 < nw; g0 += G) {
+      for (int jj = 0; jj < G; ++jj) {
+        const int j = g0 + jj;
+        uint32_t half[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint32_t acc = 0;
+        for (int h = 0; h < 2; ++h) {
+          uint32_t acc = 0;
 #pragma unroll
-        for (int b = 31; b >= 0; --b) {
-          const int2 o = offs[64 * j + 32 * h + b];
-          // tau of Eq. 3: for bytes p, q the difference q - p has bit 31 set
-          // exactly when p > q; alignbit shifts that bit into acc.
-          const uint32_t diff = static_cast<uint32_t>(centre[o.y]) - centre[o.x];
-          acc = __builtin_amdgcn_alignbit(acc, diff, 31);
+          for (int b = 31; b >= 0; --b) {
+            const int2 o = offs[64 * j + 32 * h + b];
+            // tau of Eq. 3: for bytes p, q the difference q - p has bit 31
+            // set exactly when p > q; alignbit shifts that bit into acc.
+            const uint32_t diff = static_cast<uint32_t>(centre[o.y]) - centre[o.x];
+            acc = __builtin_amdgcn_alignbit(acc, diff, 31);
+          }
+          half[h] = acc;
         }
-        half[h] = acc;
+        stage[lane * kRightStagePitch + jj] = (static_cast<uint64_t>(half[1]) << 32) | half[0];
       }
-      if (u < W) out[j] = (static_cast<uint64_t>(half[1]) << 32) | half[0];
+      // Copy the group out: pixel p's words g0 .. g0+G-1 are contiguous in
+      // global memory, so consecutive lanes write consecutive 16-byte chunks
+      // (the staging writes and reads are by the same wave, in order).
+      if (G % 2 == 0) {
+        const int per_px = G / 2, chunks = valid * per_px;
+        for (int c = lane; c < chunks; c += 64) {
+          const int p = c / per_px, part = c - p * per_px;
+          const uint64_t *src = stage + p * kRightStagePitch + 2 * part;
+          *reinterpret_cast<ulonglong2 *>(row_out + (size_t)p * nw + g0 + 2 * part) =
+              make_ulonglong2(src[0], src[1]);
+        }
+      } else {
+        const int chunks = valid * G;
+        for (int c = lane; c < chunks; c += 64) {
+          const int p = c / G, part = c - p * G;
+          row_out[(size_t)p * nw + g0 + part] = stage[p * kRightStagePitch + part];
+        }
+      }
     }
   }
 }
@@ -323,6 +357,7 @@ __global__ __launch_bounds__(kRightThreads) void k_describe_right(
 // wanted, is stored [d][v][u], so the two int16 costs of a lane form one
 // coalesced 32-bit store per step.
 // ---------------------------------------------------------------------------
+constexpr int kXcds = 8;         // accelerator complex dies of an MI355X
 constexpr int kCostTX = 128;     // pixels per wave
 constexpr int kCostDC = 64;      // disparities per LDS window
 constexpr int kCostHP = 97;      // words per parity half (>= (127 + 64) / 2, odd)
@@ -497,8 +532,16 @@ __global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict
                                                       int16_t *__restrict__ cost) {
   extern __shared__ uint64_t win[];
   const int lane = threadIdx.x;
-  const int v = blockIdx.y;
-  const int u0 = blockIdx.x * kCostTX;
+  // XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin by
+  // id, so ids b, b + 8, b + 16, ... share one XCD and its L2.  Rows are dealt
+  // the same way (row v to XCD v mod 8) and all tiles of a row go to that
+  // XCD, so the row's right descriptors, which every tile of the row reads
+  // with a dmax halo, are fetched from HBM into a single L2.
+  const int tiles = (W + kCostTX - 1) / kCostTX;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / tiles);
+  if (v >= H) return;  // whole block: ids past the last row of this XCD
+  const int u0 = (slot % tiles) * kCostTX;
   CostLane<NW> s;
   s.a = u0 + 2 * lane;
   s.b = s.a + 1;
@@ -607,7 +650,8 @@ hipError_t launch_describe_mask(const uint32_t *packed, int W, int H, const Devi
 template <int NW>
 hipError_t launch_cost_fast(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
                             int W, int H, int dmax, int32_t *disp, int16_t *cost, hipStream_t s) {
-  dim3 grid((W + kCostTX - 1) / kCostTX, H);
+  const int tiles = (W + kCostTX - 1) / kCostTX;
+  dim3 grid(kXcds * tiles * ((H + kXcds - 1) / kXcds));
   const size_t lds = (size_t)NW * 2 * kCostHP * sizeof(uint64_t);
 #define BSM_LAUNCH_COST(M, V)                                                                     \
   hipLaunchKernelGGL((k_cost_wta_fast<NW, M, V>), grid, dim3(64), lds, s, descL, maskL, descR, W, \
@@ -639,8 +683,11 @@ hipError_t launch_color(const uint8_t *img, int W, int H, int stride, uint32_t *
 hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTables &t,
                            uint64_t *desc, uint64_t *mask, hipStream_t s) {
   if (!mask) {
-    const size_t lds =
-        (size_t)t.n * sizeof(int2) + (size_t)(kRightTH + 2 * t.radius) * t.right_pitch;
+    const size_t lds = right_lds_bytes(t.n, t.radius, t.right_pitch);
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_describe_right),
+        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     dim3 grid((W + kRightTW - 1) / kRightTW, (H + kRightTH - 1) / kRightTH);
     hipLaunchKernelGGL(k_describe_right, grid, dim3(kRightThreads), lds, s, packed, W, H,
                        t.right_offs, t.nw, t.radius, t.right_pitch, desc);
