@@ -176,12 +176,39 @@ bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                      int32_t W, int32_t H, int32_t stride, int32_t dmax,
                      int32_t *disp, int16_t *cost, void *hip_stream);
 
-/* Many pairs of uneven size and dmax in one persistent launch over a device
- * work queue (captured once per batch shape into a HIP graph and replayed).
- * All pointers in `pairs` are device pointers; `pairs` itself is host
- * memory.  Results equal npairs calls of bsm_match. */
+/* Many pairs of uneven size and dmax at once.  The tiles of all pairs go
+ * into device work queues (largest pair first) served by one persistent
+ * kernel per stage (colour, describe+mask, describe, cost+WTA); the four
+ * launches are captured once per context into a HIP graph that every later
+ * batch replays, whatever its shapes.  All pointers in `pairs` are device
+ * pointers; `pairs` itself is host memory.  Results equal npairs calls of
+ * bsm_match.  Needs n in {64, 128, 256, 512, 1024}; other n run the pairs
+ * one after another.  Uses context scratch (the sum of the pairs'
+ * bsm_footprint without volumes). */
 bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs,
                            int32_t npairs, void *hip_stream);
+
+/* Launch choices of a context.  They change speed only, never results. */
+typedef struct {
+    int32_t desc_tile_w;      /* describe+mask tile width: 16 or 32 pixels   */
+    int32_t cost_dchunk;      /* disparities per cost LDS window: 32 or 64  */
+    int32_t blocks_per_cu[4]; /* workgroups per CU of the persistent batch
+                                 stages (colour, describe+mask, describe,
+                                 cost); 0 = as many as fit, max 64          */
+} bsm_tuning;
+
+bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out);
+/* BSM_EINVAL on values outside the ranges above. */
+bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *tuning);
+
+/* Autotuner: times bsm_match_batch on `pairs` (device pointers, as for
+ * bsm_match_batch; outputs are overwritten) for each candidate tuning,
+ * `reps` timed runs each, keeps the fastest on the context and returns it
+ * in *best with its mean time per batch in *best_ms (either may be NULL).
+ * Blocks until done. */
+bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t npairs,
+                        int32_t reps, void *hip_stream, bsm_tuning *best,
+                        double *best_ms);
 
 /* Serving: admission cap on the device working set of pairs in flight
  * (bytes; default 32 GiB) and the maximum number of queued requests. */

@@ -19,7 +19,8 @@ INVALID_COST = 32767
 # Every symbol include/bsm.h declares.
 EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
            "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
-           "bsm_match_batch", "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain")
+           "bsm_match_batch", "bsm_get_tuning", "bsm_set_tuning", "bsm_autotune",
+           "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain")
 
 
 class BsmError(RuntimeError):
@@ -43,6 +44,24 @@ class Pair(C.Structure):
 class Times(C.Structure):
     _fields_ = [("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_start", C.c_double),
                 ("t_end", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("desc_tile_w", C.c_int32), ("cost_dchunk", C.c_int32),
+                ("blocks_per_cu", C.c_int32 * 4)]
+
+    def as_dict(self):
+        return {"desc_tile_w": self.desc_tile_w, "cost_dchunk": self.cost_dchunk,
+                "blocks_per_cu": list(self.blocks_per_cu)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        t.desc_tile_w = int(d["desc_tile_w"])
+        t.cost_dchunk = int(d["cost_dchunk"])
+        for i, v in enumerate(d.get("blocks_per_cu", [0, 0, 0, 0])):
+            t.blocks_per_cu[i] = int(v)
+        return t
 
 
 _lib = None
@@ -72,6 +91,10 @@ def load():
         "bsm_cost_wta": ([vp, vp, vp, vp, i32, i32, i32, vp, vp, vp], st),
         "bsm_match": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
         "bsm_match_batch": ([vp, C.POINTER(Pair), i32, vp], st),
+        "bsm_get_tuning": ([vp, C.POINTER(Tuning)], st),
+        "bsm_set_tuning": ([vp, C.POINTER(Tuning)], st),
+        "bsm_autotune": ([vp, C.POINTER(Pair), i32, i32, vp, C.POINTER(Tuning),
+                          C.POINTER(C.c_double)], st),
         "bsm_serve_config": ([vp, sz, i32], st),
         "bsm_submit": ([vp, C.POINTER(Pair), C.POINTER(u64)], st),
         "bsm_poll": ([vp, u64, C.POINTER(i32), C.POINTER(Times)], st),
@@ -155,6 +178,24 @@ def bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
 def bsm_match_batch(ctx, pairs, stream):
     arr = (Pair * len(pairs))(*pairs)
     return load().bsm_match_batch(ctx, arr, len(pairs), stream)
+
+
+def bsm_get_tuning(ctx):
+    t = Tuning()
+    _check(load().bsm_get_tuning(ctx, C.byref(t)), "bsm_get_tuning")
+    return t
+
+
+def bsm_set_tuning(ctx, tuning):
+    return load().bsm_set_tuning(ctx, C.byref(tuning))
+
+
+def bsm_autotune(ctx, pairs, reps, stream):
+    arr = (Pair * len(pairs))(*pairs)
+    best = Tuning()
+    ms = C.c_double()
+    st = load().bsm_autotune(ctx, arr, len(pairs), reps, stream, C.byref(best), C.byref(ms))
+    return st, best, ms.value
 
 
 def bsm_serve_config(ctx, cap_bytes, max_queue):
@@ -277,9 +318,22 @@ class Context:
                          _ptr(cost), _stream(stream)), "bsm_match")
         return disp, cost
 
-    def match_batch(self, items, want_cost=False, stream=None):
-        """items: list of (left, right, dmax) CUDA tensors; returns a list of
-        (disp, cost)."""
+    def tuning(self):
+        return bsm_get_tuning(self.h).as_dict()
+
+    def set_tuning(self, d):
+        _check(bsm_set_tuning(self.h, Tuning.from_dict(d)), "bsm_set_tuning")
+
+    def autotune(self, items, reps=3, stream=None):
+        """Times the batch path on items (list of (left, right, dmax)) for each
+        candidate tuning and keeps the fastest; returns (tuning dict, ms)."""
+        pairs, _, keep = self._pairs(items, False)
+        st, best, ms = bsm_autotune(self.h, pairs, reps, _stream(stream))
+        _check(st, "bsm_autotune")
+        del keep
+        return best.as_dict(), ms
+
+    def _pairs(self, items, want_cost):
         import torch
         pairs, outs, keep = [], [], []
         for left, right, dmax in items:
@@ -288,9 +342,15 @@ class Context:
             disp = torch.empty((H, W), dtype=torch.int32, device=left.device)
             cost = torch.empty((dmax, H, W), dtype=torch.int16, device=left.device) \
                 if want_cost else None
-            keep += [left, right]
+            keep += [left, right, disp, cost]
             outs.append((disp, cost))
             pairs.append(Pair(left.data_ptr(), right.data_ptr(), W, H, st, dmax,
                               disp.data_ptr(), None if cost is None else cost.data_ptr()))
+        return pairs, outs, keep
+
+    def match_batch(self, items, want_cost=False, stream=None):
+        """items: list of (left, right, dmax) CUDA tensors; returns a list of
+        (disp, cost)."""
+        pairs, outs, keep = self._pairs(items, want_cost)
         _check(bsm_match_batch(self.h, pairs, _stream(stream)), "bsm_match_batch")
         return outs

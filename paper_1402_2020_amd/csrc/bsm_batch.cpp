@@ -1,14 +1,273 @@
-// Batched matching of many uneven pairs (bsm_match_batch).
+// Batched matching of many uneven pairs (bsm_match_batch) and the autotuner.
+//
+// A batch is described to the device by a work list (BatchWork): the pairs
+// with their scratch planes, a scheduling order (largest W*H*dmax first) and
+// per-queue prefix sums of tile counts.  The persistent stage kernels read
+// everything from that list, so their launches never change with the batch:
+// they are captured once into a HIP graph and replayed for every batch.  The
+// list travels host -> device through a pinned staging buffer just before
+// the graph launch, on the same stream.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
 #include "bsm_internal.h"
 
 namespace bsm {
 
+namespace {
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+}  // namespace
+
 struct BatchState {
-  Scratch scratch;
+  Scratch scratch;               // per-pair planes and descriptors
+  BatchWork *d_work = nullptr;   // fixed device address, captured in the graph
+  char *d_tables = nullptr;      // pairs | order | start | counters
+  size_t d_tables_cap = 0;
+  char *h_stage = nullptr;       // pinned staging of BatchWork + tables
+  size_t h_stage_cap = 0;
+  hipEvent_t done = nullptr;     // last batch finished with the tables
+  bool launched = false;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  ~BatchState() {
+    if (done) {
+      if (launched) (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture) (void)hipStreamDestroy(capture);
+    if (d_work) (void)hipFree(d_work);
+    if (d_tables) (void)hipFree(d_tables);
+    if (h_stage) (void)hipHostFree(h_stage);
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
 };
 
 void batch_state_free(BatchState *b) { delete b; }
 
+void batch_invalidate(bsm_ctx *ctx) {
+  if (ctx && ctx->batch) {
+    if (ctx->batch->launched) (void)hipEventSynchronize(ctx->batch->done);
+    ctx->batch->drop_graph();
+  }
+}
+
+namespace {
+
+// Scratch bytes of one pair in a batch: both colour planes, descriptors of
+// both views and the left mask.
+size_t pair_scratch_bytes(const bsm_ctx *ctx, int W, int H) {
+  const size_t px = (size_t)W * H;
+  return 2 * align_up(px * 4, 256) + 3 * align_up(px * ctx->nw * 8, 256);
+}
+
+bsm_status validate_pairs(const bsm_pair *pairs, int npairs) {
+  if (npairs < 0 || (npairs > 0 && !pairs)) return fail(BSM_EINVAL, "invalid pair list");
+  for (int i = 0; i < npairs; ++i) {
+    const bsm_pair &p = pairs[i];
+    bsm_status st;
+    if ((st = validate_image(p.left, p.width, p.height, p.stride)) != BSM_OK ||
+        (st = validate_image(p.right, p.width, p.height, p.stride)) != BSM_OK ||
+        (st = validate_dmax(p.width, p.dmax)) != BSM_OK)
+      return fail(st, "pair %d: %s", i, bsm_last_error());
+    if (!p.disp || (reinterpret_cast<uintptr_t>(p.disp) & 3u) ||
+        (reinterpret_cast<uintptr_t>(p.cost) & 3u))
+      return fail(BSM_EINVAL, "pair %d: misaligned or NULL output", i);
+  }
+  return BSM_OK;
+}
+
+// Pairs one after another (n outside the batch kernels' range).
+bsm_status batch_sequential(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hipStream_t s) {
+  size_t need = 0;
+  for (int i = 0; i < npairs; ++i)
+    need = std::max(need, match_scratch_bytes(ctx, pairs[i].width, pairs[i].height));
+  hipError_t e;
+  void *buf = ctx->batch->scratch.acquire(need, s, &e);
+  if (!buf) return device_fail(ctx, e, "batch scratch");
+  for (int i = 0; i < npairs; ++i) {
+    const bsm_pair &p = pairs[i];
+    bsm_status st = match_on_stream(ctx, p.left, p.right, p.width, p.height, p.stride, p.dmax,
+                                    p.disp, p.cost, buf, s);
+    if (st != BSM_OK) return st;
+  }
+  if ((e = ctx->batch->scratch.release(s)) != hipSuccess)
+    return device_fail(ctx, e, "batch scratch event");
+  return BSM_OK;
+}
+
+bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hipStream_t s) {
+  BatchState &b = *ctx->batch;
+  const int use_mask = ctx->use_mask;
+  hipError_t e;
+
+  // Schedule: largest cost work first, so the longest tiles start early.
+  std::vector<int> order(npairs);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const double wx = (double)pairs[x].width * pairs[x].height * pairs[x].dmax;
+    const double wy = (double)pairs[y].width * pairs[y].height * pairs[y].dmax;
+    return wx > wy;
+  });
+
+  // Scratch planes of every pair.
+  std::vector<size_t> offset(npairs);
+  size_t total = 0;
+  for (int i = 0; i < npairs; ++i) {
+    offset[i] = total;
+    total += pair_scratch_bytes(ctx, pairs[i].width, pairs[i].height);
+  }
+  void *scratch = b.scratch.acquire(total, s, &e);
+  if (!scratch) return device_fail(ctx, e, "batch scratch");
+
+  // Table layout (device and pinned staging alike).
+  const size_t n1 = npairs + 1;
+  const size_t off_pairs = 0;
+  const size_t off_order = align_up(off_pairs + npairs * sizeof(BatchPair), 256);
+  const size_t off_start = align_up(off_order + npairs * sizeof(int), 256);
+  const size_t off_count = align_up(off_start + kBatchQueues * n1 * sizeof(int), 256);
+  const size_t table_bytes = align_up(off_count + kBatchQueues * sizeof(int), 256);
+  const size_t stage_bytes = table_bytes + sizeof(BatchWork);
+
+  // The previous batch must be done with the staging buffer and the tables
+  // before either is rewritten.
+  if (b.launched && (e = hipEventSynchronize(b.done)) != hipSuccess)
+    return device_fail(ctx, e, "waiting for the previous batch");
+  if (table_bytes > b.d_tables_cap) {
+    if (b.d_tables) (void)hipFree(b.d_tables);
+    b.d_tables = nullptr;
+    b.d_tables_cap = 0;
+    if ((e = hipMalloc(&b.d_tables, table_bytes)) != hipSuccess)
+      return device_fail(ctx, e, "batch tables");
+    b.d_tables_cap = table_bytes;
+  }
+  if (stage_bytes > b.h_stage_cap) {
+    if (b.h_stage) (void)hipHostFree(b.h_stage);
+    b.h_stage = nullptr;
+    b.h_stage_cap = 0;
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&b.h_stage), stage_bytes,
+                           hipHostMallocDefault)) != hipSuccess)
+      return device_fail(ctx, e, "batch staging buffer");
+    b.h_stage_cap = stage_bytes;
+  }
+
+  char *h = b.h_stage;
+  BatchPair *hp = reinterpret_cast<BatchPair *>(h + off_pairs);
+  int *horder = reinterpret_cast<int *>(h + off_order);
+  int *hstart = reinterpret_cast<int *>(h + off_start);
+  for (int i = 0; i < npairs; ++i) {
+    const bsm_pair &p = pairs[i];
+    const size_t px = (size_t)p.width * p.height;
+    char *base = static_cast<char *>(scratch) + offset[i];
+    BatchPair &q = hp[i];
+    q.left = p.left;
+    q.right = p.right;
+    q.W = p.width;
+    q.H = p.height;
+    q.stride = p.stride;
+    q.dmax = p.dmax;
+    q.disp = p.disp;
+    q.cost = p.cost;
+    q.packedL = reinterpret_cast<uint32_t *>(base);
+    q.packedR = reinterpret_cast<uint32_t *>(base + align_up(px * 4, 256));
+    char *d0 = base + 2 * align_up(px * 4, 256);
+    const size_t db = align_up(px * ctx->nw * 8, 256);
+    q.descL = reinterpret_cast<uint64_t *>(d0);
+    q.maskL = reinterpret_cast<uint64_t *>(d0 + db);
+    q.descR = reinterpret_cast<uint64_t *>(d0 + 2 * db);
+  }
+  for (int q = 0; q < kBatchQueues; ++q) hstart[q * n1] = 0;
+  for (int i = 0; i < npairs; ++i) {
+    const bsm_pair &p = pairs[order[i]];
+    horder[i] = order[i];
+    int counts[kBatchQueues];
+    batch_tile_counts(p.width, p.height, use_mask, p.cost != nullptr, ctx->dt.tune.desc_tile_w,
+                      counts);
+    for (int q = 0; q < kBatchQueues; ++q) hstart[q * n1 + i + 1] = hstart[q * n1 + i] + counts[q];
+  }
+  std::memset(h + off_count, 0, kBatchQueues * sizeof(int));
+  BatchWork *hw = reinterpret_cast<BatchWork *>(h + table_bytes);
+  hw->pairs = reinterpret_cast<const BatchPair *>(b.d_tables + off_pairs);
+  hw->order = reinterpret_cast<const int *>(b.d_tables + off_order);
+  hw->start = reinterpret_cast<const int *>(b.d_tables + off_start);
+  hw->counters = reinterpret_cast<int *>(b.d_tables + off_count);
+  hw->npairs = npairs;
+
+  if ((e = hipMemcpyAsync(b.d_tables, h, table_bytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(b.d_work, hw, sizeof(BatchWork), hipMemcpyHostToDevice, s)) !=
+          hipSuccess)
+    return device_fail(ctx, e, "uploading the batch work list");
+
+  const BatchLaunch bl{b.d_work, hw->counters};
+  if (!b.exec) {
+    // Capture the stage launches once; they read everything else from the
+    // work list, so the graph serves every later batch of this context.
+    if ((e = hipStreamBeginCapture(b.capture, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return device_fail(ctx, e, "beginning batch graph capture");
+    hipError_t le = launch_batch(bl, ctx->dt, use_mask, b.capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b.capture, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return device_fail(ctx, le != hipSuccess ? le : e, "capturing the batch graph");
+    }
+    b.graph = g;
+    if ((e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0)) != hipSuccess) {
+      b.drop_graph();
+      return device_fail(ctx, e, "instantiating the batch graph");
+    }
+  }
+  if ((e = hipGraphLaunch(b.exec, s)) != hipSuccess)
+    return device_fail(ctx, e, "launching the batch graph");
+  if ((e = hipEventRecord(b.done, s)) != hipSuccess) return device_fail(ctx, e, "batch event");
+  b.launched = true;
+  if ((e = b.scratch.release(s)) != hipSuccess) return device_fail(ctx, e, "batch scratch event");
+  return BSM_OK;
+}
+
+bsm_status ensure_batch_state(bsm_ctx *ctx) {
+  if (ctx->batch) return BSM_OK;
+  std::unique_ptr<BatchState> b(new BatchState);
+  hipError_t e;
+  if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipMalloc(&b->d_work, sizeof(BatchWork))) != hipSuccess)
+    return device_fail(ctx, e, "batch state");
+  ctx->batch = b.release();
+  return BSM_OK;
+}
+
+bsm_status run_batch(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hipStream_t s) {
+  bsm_status st = ensure_batch_state(ctx);
+  if (st != BSM_OK) return st;
+  if (!batch_supported(ctx->nw)) return batch_sequential(ctx, pairs, npairs, s);
+  return batch_persistent(ctx, pairs, npairs, s);
+}
+
+// RAII device switch for the entry points of this file.
+struct OnDevice {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit OnDevice(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~OnDevice() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
 }  // namespace bsm
 
 using namespace bsm;
@@ -18,35 +277,73 @@ extern "C" bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs, int32
   clear_error();
   bsm_status st;
   if ((st = check_alive(ctx)) != BSM_OK) return st;
-  if (npairs < 0 || (npairs > 0 && !pairs)) return fail(BSM_EINVAL, "invalid pair list");
-  size_t need = 0;
-  for (int i = 0; i < npairs; ++i) {
-    const bsm_pair &p = pairs[i];
-    if ((st = validate_image(p.left, p.width, p.height, p.stride)) != BSM_OK ||
-        (st = validate_image(p.right, p.width, p.height, p.stride)) != BSM_OK ||
-        (st = validate_dmax(p.width, p.dmax)) != BSM_OK)
-      return fail(st, "pair %d: %s", i, bsm_last_error());
-    if (!p.disp || (reinterpret_cast<uintptr_t>(p.disp) & 3u) ||
-        (reinterpret_cast<uintptr_t>(p.cost) & 3u))
-      return fail(BSM_EINVAL, "pair %d: misaligned or NULL output", i);
-    need = std::max(need, match_scratch_bytes(ctx, p.width, p.height));
-  }
+  if ((st = validate_pairs(pairs, npairs)) != BSM_OK) return st;
   if (npairs == 0) return BSM_OK;
-  if (!ctx->batch) ctx->batch = new BatchState;
-  int prev = -1;
-  (void)hipGetDevice(&prev);
-  if (prev != ctx->device) (void)hipSetDevice(ctx->device);
+  OnDevice g(ctx->device);
+  if (g.err != hipSuccess) return device_fail(ctx, g.err, "hipSetDevice");
+  return run_batch(ctx, pairs, npairs, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t npairs,
+                                   int32_t reps, void *hip_stream, bsm_tuning *best,
+                                   double *best_ms) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_pairs(pairs, npairs)) != BSM_OK) return st;
+  if (npairs < 1 || reps < 1 || reps > 1000)
+    return fail(BSM_EINVAL, "need npairs >= 1 and 1 <= reps <= 1000");
+  OnDevice g(ctx->device);
+  if (g.err != hipSuccess) return device_fail(ctx, g.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e;
-  void *buf = ctx->batch->scratch.acquire(need, s, &e);
-  if (!buf) st = device_fail(ctx, e, "batch scratch");
-  for (int i = 0; st == BSM_OK && i < npairs; ++i) {
-    const bsm_pair &p = pairs[i];
-    st = match_on_stream(ctx, p.left, p.right, p.width, p.height, p.stride, p.dmax, p.disp,
-                         p.cost, buf, s);
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return device_fail(ctx, e, "autotune events");
   }
-  if (st == BSM_OK && (e = ctx->batch->scratch.release(s)) != hipSuccess)
-    st = device_fail(ctx, e, "batch scratch event");
-  if (prev >= 0 && prev != ctx->device) (void)hipSetDevice(prev);
-  return st;
+  const Tuning start = ctx->dt.tune;
+  Tuning best_t = start;
+  double best_time = -1;
+  // Candidates: describe tile width x cost window x cost / describe+mask
+  // persistent occupancy.
+  for (int tw : {16, 32})
+    for (int dc : {32, 64})
+      for (int cost_bpc : {0, 2})
+        for (int mask_bpc : {0, 2}) {
+          Tuning t;
+          t.desc_tile_w = tw;
+          t.cost_dchunk = dc;
+          t.blocks_per_cu[1] = mask_bpc;
+          t.blocks_per_cu[3] = cost_bpc;
+          ctx->dt.tune = t;
+          batch_invalidate(ctx);
+          // one untimed run (captures the graph), then the timed runs
+          if ((st = run_batch(ctx, pairs, npairs, s)) != BSM_OK) break;
+          if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+          for (int r = 0; r < reps && st == BSM_OK; ++r) st = run_batch(ctx, pairs, npairs, s);
+          if (st != BSM_OK) break;
+          if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
+            break;
+          float ms = 0;
+          if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+          const double per = ms / reps;
+          if (best_time < 0 || per < best_time) {
+            best_time = per;
+            best_t = t;
+          }
+        }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st == BSM_OK && e != hipSuccess) st = device_fail(ctx, e, "autotune timing");
+  ctx->dt.tune = st == BSM_OK ? best_t : start;
+  batch_invalidate(ctx);
+  if (st != BSM_OK) return st;
+  if (best) {
+    best->desc_tile_w = best_t.desc_tile_w;
+    best->cost_dchunk = best_t.cost_dchunk;
+    for (int i = 0; i < 4; ++i) best->blocks_per_cu[i] = best_t.blocks_per_cu[i];
+  }
+  if (best_ms) *best_ms = best_time;
+  return BSM_OK;
 }

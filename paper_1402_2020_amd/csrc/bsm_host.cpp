@@ -290,7 +290,8 @@ bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left, const uint8_t *rig
     return device_fail(ctx, e, "colour pre-pass (right)");
   if ((e = launch_describe(packed, W, H, ctx->dt, descR, nullptr, s)) != hipSuccess)
     return device_fail(ctx, e, "describe (right)");
-  if ((e = launch_cost_wta(descL, m ? maskL : nullptr, descR, W, H, ctx->nw, dmax, disp, cost, s)) !=
+  if ((e = launch_cost_wta(descL, m ? maskL : nullptr, descR, W, H, ctx->nw, dmax, disp, cost,
+                           ctx->dt, s)) !=
       hipSuccess)
     return device_fail(ctx, e, "cost + WTA");
   return BSM_OK;
@@ -362,7 +363,10 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
 
   // LDS layouts of the describe kernels: the pitch of the descriptor+mask
   // tile is chosen for this pattern; the intensity tile needs no padding.
-  const int left_pitch = choose_left_pitch(ctx->pattern.data(), ctx->n, describe_left_cols(radius));
+  const int left_pitch16 =
+      choose_left_pitch(ctx->pattern.data(), ctx->n, describe_left_cols(radius, 16));
+  const int left_pitch32 =
+      choose_left_pitch(ctx->pattern.data(), ctx->n, describe_left_cols(radius, 32));
   const int right_pitch = describe_right_cols(radius);
   std::vector<int2> right_offs(ctx->n);
   for (int i = 0; i < ctx->n; ++i) {
@@ -396,7 +400,8 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
   dt.lin = ctx->d_lin;
   dt.f = ctx->d_f;
   dt.right_offs = ctx->d_right_offs;
-  dt.left_pitch = left_pitch;
+  dt.left_pitch16 = left_pitch16;
+  dt.left_pitch32 = left_pitch32;
   dt.right_pitch = right_pitch;
   std::memcpy(dt.mq.m, ctx->tables.mq, sizeof dt.mq.m);
   dt.n = ctx->n;
@@ -504,9 +509,40 @@ bsm_status bsm_cost_wta(bsm_ctx *ctx, const uint64_t *descL, const uint64_t *mas
     return fail(BSM_EINVAL, "misaligned device pointer");
   DeviceGuard g(ctx->device);
   if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
-  hipError_t e = launch_cost_wta(descL, maskL, descR, W, H, ctx->nw, dmax, disp, cost,
+  hipError_t e = launch_cost_wta(descL, maskL, descR, W, H, ctx->nw, dmax, disp, cost, ctx->dt,
                                  static_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? BSM_OK : device_fail(ctx, e, "cost + WTA");
+}
+
+bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out) {
+  clear_error();
+  if (!ctx || !out) return fail(BSM_EINVAL, "context and out must not be NULL");
+  const Tuning &t = ctx->dt.tune;
+  out->desc_tile_w = t.desc_tile_w;
+  out->cost_dchunk = t.cost_dchunk;
+  for (int i = 0; i < 4; ++i) out->blocks_per_cu[i] = t.blocks_per_cu[i];
+  return BSM_OK;
+}
+
+bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *in) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if (!in) return fail(BSM_EINVAL, "tuning must not be NULL");
+  if (in->desc_tile_w != 16 && in->desc_tile_w != 32)
+    return fail(BSM_EINVAL, "desc_tile_w must be 16 or 32");
+  if (in->cost_dchunk != 32 && in->cost_dchunk != 64)
+    return fail(BSM_EINVAL, "cost_dchunk must be 32 or 64");
+  for (int i = 0; i < 4; ++i)
+    if (in->blocks_per_cu[i] < 0 || in->blocks_per_cu[i] > 64)
+      return fail(BSM_EINVAL, "blocks_per_cu[%d] out of [0, 64]", i);
+  Tuning t;
+  t.desc_tile_w = in->desc_tile_w;
+  t.cost_dchunk = in->cost_dchunk;
+  for (int i = 0; i < 4; ++i) t.blocks_per_cu[i] = in->blocks_per_cu[i];
+  ctx->dt.tune = t;
+  batch_invalidate(ctx);  // a captured batch graph holds the old launch shapes
+  return BSM_OK;
 }
 
 bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, int32_t W, int32_t H,

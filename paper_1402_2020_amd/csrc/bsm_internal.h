@@ -41,6 +41,13 @@ struct Mq {
   int32_t m[9];
 };
 
+// Launch choices the autotuner may change (all results are identical).
+struct Tuning {
+  int desc_tile_w = 16;                // describe+mask tile width: 16 or 32 pixels
+  int cost_dchunk = 64;                // disparities per cost LDS window: 32 or 64
+  int blocks_per_cu[4] = {0, 0, 0, 0};  // persistent batch grids (0: all that fit)
+};
+
 // Device-side view of the constant data of a context.
 struct DeviceTables {
   const int8_t *pattern;   // [n][4]
@@ -49,16 +56,52 @@ struct DeviceTables {
   const int2 *right_offs;  // [n] (p, q) byte offsets in the intensity tile
   Mq mq;
   int n, nw, k, radius;
-  int left_pitch;   // LDS row pitch (words) of the descriptor+mask tile
-  int right_pitch;  // LDS row pitch (bytes) of the intensity tile
+  int left_pitch16, left_pitch32;  // LDS row pitch (words) of the descriptor+mask
+                                   // tile for tile widths 16 and 32
+  int right_pitch;                 // LDS row pitch (bytes) of the intensity tile
+  Tuning tune;
+  int left_pitch_for(int tile_w) const { return tile_w == 32 ? left_pitch32 : left_pitch16; }
 };
 
 // Tile geometry of the describe kernels (bsm_kernels.hip).
-int describe_left_cols(int radius);   // tile width incl. halo, in pixels
+int describe_left_cols(int radius, int tile_w);  // tile width incl. halo, pixels
 int describe_right_cols(int radius);
 // LDS pitch (pixels) for the descriptor+mask tile that minimises the bank
 // conflicts of the pattern's gathers (host search, bsm_host.cpp).
 int choose_left_pitch(const int8_t *pattern, int n, int cols);
+
+// ---- batch work lists (device memory) -------------------------------------
+// Queues of the persistent batch kernels.  Cost tiles have one queue per
+// XCD, separately for pairs without and with a cost volume.
+constexpr int kQueueColor = 0, kQueueDescribeMask = 1, kQueueDescribe = 2, kQueueCost0 = 3;
+constexpr int kQueueCostVol0 = kQueueCost0 + 8;
+constexpr int kBatchQueues = kQueueCostVol0 + 8;
+
+// One pair of a batch with its scratch planes.
+struct BatchPair {
+  const uint8_t *left, *right;
+  int32_t W, H, stride, dmax;
+  int32_t *disp;
+  int16_t *cost;
+  uint32_t *packedL, *packedR;
+  uint64_t *descL, *maskL, *descR;
+};
+
+// The work list: pairs in scheduling order and, per queue, the prefix sums
+// of their tile counts (start[q * (npairs + 1) + i]).
+struct BatchWork {
+  const BatchPair *pairs;
+  const int *order;
+  const int *start;
+  int *counters;  // [kBatchQueues]
+  int npairs;
+};
+
+// Host-side handle of a device BatchWork.
+struct BatchLaunch {
+  const BatchWork *work;  // device pointer
+  int *counters;          // device pointer (== work->counters)
+};
 
 // ---- kernel launchers (bsm_kernels.hip) -----------------------------------
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride,
@@ -70,11 +113,20 @@ hipError_t launch_describe(const uint32_t *packed, int W, int H,
 hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL,
                            const uint64_t *descR, int W, int H, int nw,
                            int dmax, int32_t *disp, int16_t *cost,
-                           hipStream_t s);
+                           const DeviceTables &t, hipStream_t s);
+// The four persistent stage kernels of a batch (after a counter reset).
+hipError_t launch_batch(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
+                        hipStream_t s);
+bool batch_supported(int nw);
+// Tiles per stage of one pair, as the batch kernels number them.
+void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
+                       int counts[kBatchQueues]);
 
-// ---- batch (bsm_batch.hip) --------------------------------------------------
+// ---- batch (bsm_batch.cpp) --------------------------------------------------
 struct BatchState;
 void batch_state_free(BatchState *b);
+// Drops the captured batch graph (launch shapes changed).
+void batch_invalidate(bsm_ctx *ctx);
 
 // ---- device scratch with stream-ordered reuse ---------------------------
 // A growable device buffer.  Every use is recorded with an event; a use on

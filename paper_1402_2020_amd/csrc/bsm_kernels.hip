@@ -1,11 +1,15 @@
 // HIP kernels of the BSM hot path for gfx950 (CDNA4, wave64).
 //
-//   k_color     colour pre-pass: intensity (Eq. 3) and 8-bit CIELAB (Eq. 5)
-//   k_describe  BRIEF descriptor (Eq. 2-3) and binary mask (Eq. 5-7)
-//   k_cost_wta  masked Hamming cost (Eq. 8 / Eq. 4) fused with WTA (Eq. 1)
+//   colour        intensity (Eq. 3) and 8-bit CIELAB (Eq. 5) per pixel
+//   describe+mask BRIEF descriptor (Eq. 2-3) and binary mask (Eq. 5-7)
+//   describe      BRIEF descriptor only (the non-reference view)
+//   cost+WTA      masked Hamming cost (Eq. 8 / Eq. 4) fused with WTA (Eq. 1)
 //
-// Nothing on this path is a dense contraction, so there is no MFMA: the
-// kernels are bound by integer VALU issue (cost, descriptor) or HBM (colour).
+// Each stage is a per-tile device function.  The single-pair kernels map
+// one workgroup to one tile; the batch kernels are persistent and pull the
+// tiles of many pairs from a device work list, so both paths run the same
+// per-tile code.  Nothing here is a dense contraction, so there is no MFMA:
+// the kernels are bound by integer VALU/SALU issue or by HBM.
 #include <type_traits>
 
 #include "bsm_internal.h"
@@ -13,10 +17,14 @@
 namespace bsm {
 namespace {
 
-// ---------------------------------------------------------------------------
-// K1: colour pre-pass.  One thread per pixel; output uint32 per pixel:
-// byte 0 L8, byte 1 a8, byte 2 b8, byte 3 intensity I.
-// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
+
+// ===========================================================================
+// Colour pre-pass.  Output uint32 per pixel: byte 0 L8, byte 1 a8, byte 2 b8,
+// byte 3 intensity I.  Tiles of 64 x 16 pixels: 256 threads, 4 rows each.
+// ===========================================================================
+constexpr int kColorTX = 64, kColorTY = 16, kColorThreads = 256;
+constexpr int kColorRowsPerThread = kColorTX * kColorTY / kColorThreads;
 
 // floor((2a + b) / (2b)) for b > 0: a / b rounded to nearest, halves up.
 __device__ __forceinline__ int32_t nearest_div(int64_t a, int64_t b) {
@@ -30,43 +38,56 @@ __device__ __forceinline__ uint32_t clamp_u8(int32_t x) {
   return static_cast<uint32_t>(x < 0 ? 0 : (x > 255 ? 255 : x));
 }
 
-constexpr int kColorTX = 64, kColorTY = 4;
-
-__global__ __launch_bounds__(256) void k_color(const uint8_t *__restrict__ img, int W, int H,
-                                               int stride, uint32_t *__restrict__ out,
-                                               const uint16_t *__restrict__ lin,
-                                               const uint16_t *__restrict__ ftab, Mq mq,
-                                               int want_lab) {
-  const int u = blockIdx.x * kColorTX + (threadIdx.x % kColorTX);
-  const int v = blockIdx.y * kColorTY + (threadIdx.x / kColorTX);
-  if (u >= W || v >= H) return;
-  const uint8_t *px = img + (size_t)v * stride + 3 * (size_t)u;
-  const int32_t R = px[0], G = px[1], B = px[2];
-  uint32_t word = static_cast<uint32_t>((77 * R + 150 * G + 29 * B + 128) >> 8) << 24;
-  if (want_lab) {
-    const int32_t lr = lin[R], lg = lin[G], lb = lin[B];
-    const int32_t fx = ftab[(mq.m[0] * lr + mq.m[1] * lg + mq.m[2] * lb + 8192) >> 14];
-    const int32_t fy = ftab[(mq.m[3] * lr + mq.m[4] * lg + mq.m[5] * lb + 8192) >> 14];
-    const int32_t fz = ftab[(mq.m[6] * lr + mq.m[7] * lg + mq.m[8] * lb + 8192) >> 14];
-    const uint32_t L8 = clamp_u8(nearest_div(255 * (116 * (int64_t)fy - 16 * 65535), 100 * 65535));
-    const uint32_t a8 = clamp_u8(128 + nearest_div(500 * (int64_t)(fx - fy), 65535));
-    const uint32_t b8 = clamp_u8(128 + nearest_div(200 * (int64_t)(fy - fz), 65535));
-    word |= L8 | (a8 << 8) | (b8 << 16);
+__device__ __forceinline__ void color_tile(const uint8_t *__restrict__ img, int W, int H,
+                                           int stride, uint32_t *__restrict__ out,
+                                           const uint16_t *__restrict__ lin,
+                                           const uint16_t *__restrict__ ftab, const Mq &mq,
+                                           int want_lab, int u0, int v0) {
+  const int u = u0 + (threadIdx.x % kColorTX);
+  if (u >= W) return;
+#pragma unroll
+  for (int r = 0; r < kColorRowsPerThread; ++r) {
+    const int v = v0 + r * (kColorThreads / kColorTX) + (threadIdx.x / kColorTX);
+    if (v >= H) return;
+    const uint8_t *px = img + (size_t)v * stride + 3 * (size_t)u;
+    const int32_t R = px[0], G = px[1], B = px[2];
+    uint32_t word = static_cast<uint32_t>((77 * R + 150 * G + 29 * B + 128) >> 8) << 24;
+    if (want_lab) {
+      const int32_t lr = lin[R], lg = lin[G], lb = lin[B];
+      const int32_t fx = ftab[(mq.m[0] * lr + mq.m[1] * lg + mq.m[2] * lb + 8192) >> 14];
+      const int32_t fy = ftab[(mq.m[3] * lr + mq.m[4] * lg + mq.m[5] * lb + 8192) >> 14];
+      const int32_t fz = ftab[(mq.m[6] * lr + mq.m[7] * lg + mq.m[8] * lb + 8192) >> 14];
+      const uint32_t L8 =
+          clamp_u8(nearest_div(255 * (116 * (int64_t)fy - 16 * 65535), 100 * 65535));
+      const uint32_t a8 = clamp_u8(128 + nearest_div(500 * (int64_t)(fx - fy), 65535));
+      const uint32_t b8 = clamp_u8(128 + nearest_div(200 * (int64_t)(fy - fz), 65535));
+      word |= L8 | (a8 << 8) | (b8 << 16);
+    }
+    out[(size_t)v * W + u] = word;
   }
-  out[(size_t)v * W + u] = word;
 }
 
-// ---------------------------------------------------------------------------
-// K2: descriptor and mask.  A block stages a TH x TW tile of packed pixels
-// plus a halo of `radius` in LDS (coordinates clamped to the image, which is
-// exactly the border rule).  Each wave then walks its pixels one at a time
-// with the 64 lanes spread over point pairs: lane l of word j evaluates pair
-// 64 j + l, so the wave-wide ballot of the binary test IS word j of B(x)
-// (bit l = pair 64 j + l + 1).  For the mask each lane keeps its pair
-// weights in registers and the k-th smallest weight T is found by bisection
-// on [0, 765], each probe counting ballot(w <= t) words with a popcount.
-// ---------------------------------------------------------------------------
-constexpr int kDescTW = 16, kDescTH = 8, kDescThreads = 256;
+__global__ __launch_bounds__(kColorThreads) void k_color(const uint8_t *__restrict__ img, int W,
+                                                         int H, int stride,
+                                                         uint32_t *__restrict__ out,
+                                                         const uint16_t *__restrict__ lin,
+                                                         const uint16_t *__restrict__ ftab, Mq mq,
+                                                         int want_lab) {
+  color_tile(img, W, H, stride, out, lin, ftab, mq, want_lab, blockIdx.x * kColorTX,
+             blockIdx.y * kColorTY);
+}
+
+// ===========================================================================
+// Descriptor + mask (reference view).  A block stages a TH x TW tile of
+// packed pixels plus a halo of `radius` in LDS (coordinates clamped to the
+// image, which is exactly the border rule).  Each wave walks its pixels one
+// at a time with the 64 lanes spread over point pairs: lane l of word j
+// evaluates pair 64 j + l, so the wave-wide ballot of the binary test IS
+// word j of B(x) (bit l = pair 64 j + l + 1).  Each lane keeps its pair
+// weights in registers; T, the k-th smallest weight, is found by bisection,
+// each probe counting ballot(w <= t) words with a scalar popcount.
+// ===========================================================================
+constexpr int kDescTH = 8, kDescThreads = 256;
 
 // v_writelane_b32 through the LLVM intrinsic (this clang has no builtin for
 // it), so that the compiler's hazard handling sees it: an SGPR written by a
@@ -91,11 +112,11 @@ __device__ __forceinline__ void for_words(F &&f) {
   }
 }
 
-// One pixel of the descriptor (and mask).  ap/aq: LDS byte addresses of this
+// One pixel of the descriptor and mask.  ap/aq: LDS byte addresses of this
 // lane's samples for the group's first pixel; `shift` (bytes, compile-time
 // after unrolling) moves them to this pixel through the instruction's
 // immediate offset.  out: this pixel's words in desc / mask.
-template <int NW, bool MASK>
+template <int NW>
 __device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, const int *aq,
                                                int centre_addr, int shift, int lane, int nw,
                                                int k_eff, uint64_t *out_desc,
@@ -110,52 +131,58 @@ __device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, c
   for_words<NW>([&](auto J) {  // tau of Eq. 3
     put_word<J.value>(__ballot((a[J.value] >> 24) > (b[J.value] >> 24)), d_lo, d_hi);
   });
-  uint32_t m_lo = 0, m_hi = 0;
-  if (MASK) {
-    const uint32_t centre = *reinterpret_cast<const uint32_t *>(lds + centre_addr) & 0xffffffu;
-    uint32_t w[NW];
-    uint32_t wmax = 0;
+  const uint32_t centre = *reinterpret_cast<const uint32_t *>(lds + centre_addr) & 0xffffffu;
+  uint32_t w[NW];
+  uint32_t wmax = 0;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      const uint32_t sp = __builtin_amdgcn_sad_u8(a[j] & 0xffffffu, centre, 0u);
-      const uint32_t sq = __builtin_amdgcn_sad_u8(b[j] & 0xffffffu, centre, 0u);
-      w[j] = sp > sq ? sp : sq;  // Eq. 5
-      wmax = wmax > w[j] ? wmax : w[j];
-    }
-    // T is the smallest t with #{w <= t} >= k (the k-th smallest weight).
-    // It lies in [0, max w]; search [0, 2^b - 1] for the smallest such
-    // power-of-two range, then bisect.
-    int hi = 1023;
-    while (hi > 0 && __ballot(wmax > (uint32_t)(hi >> 1)) == 0) hi >>= 1;
-    int lo = 0;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      int count = 0;
-#pragma unroll
-      for (int j = 0; j < NW; ++j) count += __popcll(__ballot(w[j] <= (uint32_t)mid));
-      if (count >= k_eff)
-        hi = mid;
-      else
-        lo = mid + 1;
-    }
-    for_words<NW>([&](auto J) {  // Eq. 6-7
-      put_word<J.value>(__ballot(w[J.value] <= (uint32_t)lo), m_lo, m_hi);
-    });
+  for (int j = 0; j < NW; ++j) {
+    const uint32_t sp = __builtin_amdgcn_sad_u8(a[j] & 0xffffffu, centre, 0u);
+    const uint32_t sq = __builtin_amdgcn_sad_u8(b[j] & 0xffffffu, centre, 0u);
+    w[j] = sp > sq ? sp : sq;  // Eq. 5
+    wmax = wmax > w[j] ? wmax : w[j];
   }
+  // T is the smallest t with #{w <= t} >= k (the k-th smallest weight).  It
+  // lies in [0, max w]; narrow [0, 1023] to the smallest power-of-two range
+  // holding max w, then bisect.
+  int hi = 1023;
+  while (hi > 0 && __ballot(wmax > (uint32_t)(hi >> 1)) == 0) hi >>= 1;
+  int lo = 0;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    int count = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) count += __popcll(__ballot(w[j] <= (uint32_t)mid));
+    if (count >= k_eff)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  uint32_t m_lo = 0, m_hi = 0;
+  for_words<NW>([&](auto J) {  // Eq. 6-7
+    put_word<J.value>(__ballot(w[J.value] <= (uint32_t)lo), m_lo, m_hi);
+  });
   if (lane < nw) {
     out_desc[lane] = (static_cast<uint64_t>(d_hi) << 32) | d_lo;
-    if (MASK) out_mask[lane] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
+    out_mask[lane] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
   }
 }
 
-template <int NW, bool MASK>
-__global__ __launch_bounds__(kDescThreads) void k_describe(
-    const uint32_t *__restrict__ packed, int W, int H, const int8_t *__restrict__ pattern, int nw,
-    int radius, int pitch, int k, uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
-  extern __shared__ uint32_t tile[];
-  const int u0 = blockIdx.x * kDescTW, v0 = blockIdx.y * kDescTH;
-  const int rows = kDescTH + 2 * radius, cols = kDescTW + 2 * radius;
+// Parameters of the describe kernels that are fixed per context.
+struct DescribeConsts {
+  const int8_t *pattern;  // [n][4]
+  int nw, radius, pitch, k;
+};
+
+template <int NW, int TW>
+__device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
+                                                   const uint32_t *__restrict__ packed, int W,
+                                                   int H, const DescribeConsts &c,
+                                                   uint64_t *__restrict__ desc,
+                                                   uint64_t *__restrict__ mask, int u0, int v0) {
+  const int radius = c.radius, pitch = c.pitch, nw = c.nw;
+  const int rows = kDescTH + 2 * radius, cols = TW + 2 * radius;
   const int total = rows * cols;
+  __syncthreads();  // the previous tile (persistent kernels) is done with LDS
   // Stage the tile with kBatch independent loads in flight per thread.
   constexpr int kBatch = 8;
   for (int first = threadIdx.x; first < total; first += kDescThreads * kBatch) {
@@ -186,7 +213,7 @@ __global__ __launch_bounds__(kDescThreads) void k_describe(
   // "pairs" compare the centre with itself, so their weight is 0 and they
   // only shift the rank of the threshold by 64 per padded word.
   int offp[NW], offq[NW];
-  const int32_t *pat32 = reinterpret_cast<const int32_t *>(pattern);
+  const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
     offp[j] = offq[j] = 0;
@@ -198,7 +225,7 @@ __global__ __launch_bounds__(kDescThreads) void k_describe(
       offq[j] = 4 * (qy * pitch + qx);
     }
   }
-  const int k_eff = k + 64 * (NW - nw);
+  const int k_eff = c.k + 64 * (NW - nw);
   __syncthreads();
 
   const char *lds = reinterpret_cast<const char *>(tile);
@@ -207,7 +234,7 @@ __global__ __launch_bounds__(kDescThreads) void k_describe(
   for (int r = 0; r < kRowsPerWave; ++r) {
     const int ty = wave * kRowsPerWave + r, v = v0 + ty;
     if (v >= H) break;  // uniform
-    for (int g = 0; g < kDescTW; g += kGroup) {
+    for (int g = 0; g < TW; g += kGroup) {
       if (u0 + g >= W) break;  // uniform
       const int c0 = 4 * ((ty + radius) * pitch + (g + radius));
       int ap[NW], aq[NW];
@@ -220,50 +247,67 @@ __global__ __launch_bounds__(kDescThreads) void k_describe(
       for (int t = 0; t < kGroup; ++t) {
         const int u = u0 + g + t;
         if (u >= W) break;  // uniform
-        describe_pixel<NW, MASK>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, nw, k_eff,
-                                 desc + ((size_t)v * W + u) * nw,
-                                 MASK ? mask + ((size_t)v * W + u) * nw : nullptr);
+        describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, nw, k_eff,
+                           desc + ((size_t)v * W + u) * nw, mask + ((size_t)v * W + u) * nw);
       }
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// K2 (descriptor only, the non-reference view).  Here the lanes run over 64
+template <int NW, int TW>
+__global__ __launch_bounds__(kDescThreads) void k_describe_mask(
+    const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
+    uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
+  extern __shared__ uint32_t tile[];
+  describe_mask_tile<NW, TW>(tile, packed, W, H, c, desc, mask, blockIdx.x * TW,
+                             blockIdx.y * kDescTH);
+}
+
+// ===========================================================================
+// Descriptor only (the non-reference view).  Here the lanes run over 64
 // consecutive pixels of a row and the point pairs are walked in a uniform
 // loop: for pair i all lanes read the intensity at the same offset from
 // their own pixel, i.e. 64 consecutive bytes of an LDS intensity tile, which
-// is free of bank conflicts.  The pair offsets (bytes in the tile) come from
-// a per-context table through scalar loads.  Each lane shifts its binary
+// is free of bank conflicts.  The pair offsets (bytes in the tile) are
+// staged in LDS and read back as broadcasts.  Each lane shifts its binary
 // tests into its own descriptor words, most significant pair first, so that
-// pair 64 j + 32 h + b ends at bit b of half h of word j.
-// ---------------------------------------------------------------------------
+// pair 64 j + 32 h + b ends at bit b of half h of word j.  Finished words
+// are staged in LDS per row and written out as whole 128-byte lines.
+// ===========================================================================
 constexpr int kRightTW = 64, kRightTH = 4, kRightThreads = 256;
-constexpr int kRightGroup = 16;               // words staged per pixel at a time
+constexpr int kRightGroup = 16;                    // words staged per pixel at a time
 constexpr int kRightStagePitch = kRightGroup + 1;  // u64 per staged pixel (odd: fewer conflicts)
 
-// LDS bytes of k_describe_right: pair offsets, per-wave output staging, tile.
+// LDS bytes of the describe-only kernels: pair offsets, per-wave output
+// staging, intensity tile.
 __host__ __device__ constexpr size_t right_lds_bytes(int n, int radius, int pitch) {
   return (size_t)n * sizeof(int2) +
          (size_t)(kRightThreads / 64) * kRightTW * kRightStagePitch * sizeof(uint64_t) +
          (size_t)(kRightTH + 2 * radius) * pitch;
 }
 
-__global__ __launch_bounds__(kRightThreads) void k_describe_right(
-    const uint32_t *__restrict__ packed, int W, int H, const int2 *__restrict__ offs_global,
-    int nw, int radius, int pitch, uint64_t *__restrict__ desc) {
-  // LDS: the pair offsets (read back as wave-uniform broadcasts, so that the
-  // only outstanding operations in the pair loop are in-order LDS reads),
-  // the output staging of each wave, then the intensity tile.
-  extern __shared__ int2 lds_offs[];
-  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds_offs + 64 * nw);
+struct RightConsts {
+  const int2 *offs;  // [n] (p, q) byte offsets in the intensity tile
+  int n, nw, radius, pitch;
+};
+
+// Copies the offset table to the start of LDS (once per block).
+__device__ __forceinline__ void stage_right_offsets(int2 *lds_offs, const RightConsts &c) {
+  for (int i = threadIdx.x; i < c.n; i += kRightThreads) lds_offs[i] = c.offs[i];
+}
+
+__device__ __forceinline__ void describe_right_tile(int2 *lds_offs,
+                                                    const uint32_t *__restrict__ packed, int W,
+                                                    int H, const RightConsts &c,
+                                                    uint64_t *__restrict__ desc, int u0, int v0) {
+  const int radius = c.radius, pitch = c.pitch, nw = c.nw;
+  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds_offs + c.n);
   uint8_t *itile = reinterpret_cast<uint8_t *>(
       stage_all + (kRightThreads / 64) * kRightTW * kRightStagePitch);
-  for (int i = threadIdx.x; i < 64 * nw; i += kRightThreads) lds_offs[i] = offs_global[i];
   const int2 *offs = lds_offs;
-  const int u0 = blockIdx.x * kRightTW, v0 = blockIdx.y * kRightTH;
   const int rows = kRightTH + 2 * radius, cols = kRightTW + 2 * radius;
   const int total = rows * cols;
+  __syncthreads();  // offsets staged; the previous tile is done with LDS
   constexpr int kBatch = 8;
   for (int first = threadIdx.x; first < total; first += kRightThreads * kBatch) {
     uint32_t staged[kBatch];
@@ -322,16 +366,16 @@ __global__ __launch_bounds__(kRightThreads) void k_describe_right(
       // (the staging writes and reads are by the same wave, in order).
       if (G % 2 == 0) {
         const int per_px = G / 2, chunks = valid * per_px;
-        for (int c = lane; c < chunks; c += 64) {
-          const int p = c / per_px, part = c - p * per_px;
+        for (int q = lane; q < chunks; q += 64) {
+          const int p = q / per_px, part = q - p * per_px;
           const uint64_t *src = stage + p * kRightStagePitch + 2 * part;
           *reinterpret_cast<ulonglong2 *>(row_out + (size_t)p * nw + g0 + 2 * part) =
               make_ulonglong2(src[0], src[1]);
         }
       } else {
         const int chunks = valid * G;
-        for (int c = lane; c < chunks; c += 64) {
-          const int p = c / G, part = c - p * G;
+        for (int q = lane; q < chunks; q += 64) {
+          const int p = q / G, part = q - p * G;
           row_out[(size_t)p * nw + g0 + part] = stage[p * kRightStagePitch + part];
         }
       }
@@ -339,28 +383,34 @@ __global__ __launch_bounds__(kRightThreads) void k_describe_right(
   }
 }
 
-// ---------------------------------------------------------------------------
-// K3 (fast): masked cost fused with winner-take-all, n = 64 NW bits,
-// NW in {1, 2, 4, 8, 16}.
+__global__ __launch_bounds__(kRightThreads) void k_describe_right(
+    const uint32_t *__restrict__ packed, int W, int H, RightConsts c,
+    uint64_t *__restrict__ desc) {
+  extern __shared__ int2 lds_offs[];
+  stage_right_offsets(lds_offs, c);
+  describe_right_tile(lds_offs, packed, W, H, c, desc, blockIdx.x * kRightTW,
+                      blockIdx.y * kRightTH);
+}
+
+// ===========================================================================
+// Masked cost fused with winner-take-all, n = 64 NW bits, NW in
+// {1, 2, 4, 8, 16}.
 //
 // One wave per (row v, 128-pixel tile).  Lane l owns the two adjacent left
 // pixels a = u0 + 2l and b = a + 1, with their B_L and Phi in registers.
 // Disparities are walked in order; at step d lane l reads B_R(a - d) from
 // LDS and uses it for (a, d) now and for (b, d + 1) at the next step, since
 // b - (d + 1) = a - d: every right descriptor fetched from LDS serves two
-// evaluations.  The right descriptors of the window a disparity chunk needs
-// sit in LDS word-major and split by parity, so at any step the 64 lanes
-// read 64 consecutive 8-byte words (no bank conflicts).  Each evaluation is
+// evaluations.  The right descriptors of the window a chunk of DC
+// disparities needs sit in LDS split by parity, so at any step the 64 lanes
+// read 64 consecutive 16-byte chunks (no bank conflicts).  Each evaluation is
 // (bl ^ br) & m per 32-bit half (one v_bitop3_b32) plus a popcount that
 // accumulates for free (v_bcnt_u32_b32); the running minimum of the key
 // (C << 16) | d gives the lowest d among equal costs.  The cost volume, when
 // wanted, is stored [d][v][u], so the two int16 costs of a lane form one
 // coalesced 32-bit store per step.
-// ---------------------------------------------------------------------------
-constexpr int kXcds = 8;         // accelerator complex dies of an MI355X
-constexpr int kCostTX = 128;     // pixels per wave
-constexpr int kCostDC = 64;      // disparities per LDS window
-constexpr int kCostHP = 97;      // words per parity half (>= (127 + 64) / 2, odd)
+// ===========================================================================
+constexpr int kCostTX = 128;  // pixels per wave
 
 // c + popcount(x) as one v_bcnt_u32_b32.  Written out so that the compiler
 // keeps one accumulating chain instead of re-associating the sum into trees
@@ -396,18 +446,22 @@ __device__ __forceinline__ uint32_t masked_cost(const uint64_t *bl, const uint64
   return c;
 }
 
-// LDS window of right descriptors.  Elements are chunks of CW consecutive
-// words of one pixel (16 bytes when n >= 128); the layout is
-// [chunk jc][parity of pixel][pixel / 2][CW words], so at every step the 64
-// lanes (which read pixels of one parity, 2 apart) touch 64 consecutive
-// chunks, and the chunk index only moves a compile-time immediate offset.
-template <int NW>
+// LDS window of right descriptors for one chunk of DC disparities.  Elements
+// are chunks of CW consecutive words of one pixel (16 bytes when n >= 128);
+// the layout is [chunk jc][parity of pixel][pixel / 2][CW words], so at every
+// step the 64 lanes (which read pixels of one parity, 2 apart) touch 64
+// consecutive chunks, and the chunk index only moves a compile-time
+// immediate offset.
+template <int NW, int DC>
 struct Window {
-  static constexpr int CW = NW >= 2 ? 2 : 1;  // words per chunk
-  static constexpr int CPP = NW / CW;          // chunks per pixel
+  static constexpr int CW = NW >= 2 ? 2 : 1;       // words per chunk
+  static constexpr int CPP = NW / CW;               // chunks per pixel
+  static constexpr int P = kCostTX - 1 + DC;         // pixels in the window
+  static constexpr int HP = (P + 1) / 2 + 1;         // pixels per parity half
+  static constexpr size_t kBytes = (size_t)CPP * 2 * HP * CW * sizeof(uint64_t);
   // u64 index of (chunk jc, relative pixel rel)
   __device__ static int index(int jc, int rel) {
-    return ((jc * 2 + (rel & 1)) * kCostHP + (rel >> 1)) * CW;
+    return ((jc * 2 + (rel & 1)) * HP + (rel >> 1)) * CW;
   }
 };
 
@@ -415,10 +469,10 @@ struct Window {
 // image) into the LDS window.  Pixel r's words are contiguous in global
 // memory, so the wave reads coalesced chunks with up to kBatch loads in
 // flight per lane before writing them to LDS.
-template <int NW>
+template <int NW, int DC>
 __device__ __forceinline__ void stage_window(const uint64_t *__restrict__ rowR, int r_lo, int P,
                                              int W, int lane, uint64_t *win) {
-  using Win = Window<NW>;
+  using Win = Window<NW, DC>;
   constexpr int kBatch = 8;
   const int total = P * Win::CPP;
   for (int first = lane; first < total; first += 64 * kBatch) {
@@ -457,9 +511,9 @@ __device__ __forceinline__ void stage_window(const uint64_t *__restrict__ rowR, 
 }
 
 // Loads the NW words of relative pixel `rel` from the window.
-template <int NW>
+template <int NW, int DC>
 __device__ __forceinline__ void load_right(const uint64_t *win, int rel, uint64_t *out) {
-  using Win = Window<NW>;
+  using Win = Window<NW, DC>;
 #pragma unroll
   for (int jc = 0; jc < Win::CPP; ++jc) {
     const uint64_t *src = win + Win::index(jc, rel);
@@ -473,7 +527,7 @@ __device__ __forceinline__ void load_right(const uint64_t *win, int rel, uint64_
   }
 }
 
-// Per-lane state of the fused cost + WTA kernel.
+// Per-lane state of the fused cost + WTA tile.
 template <int NW>
 struct CostLane {
   uint64_t bla[NW], ma[NW], blb[NW], mb[NW];
@@ -484,11 +538,11 @@ struct CostLane {
 
 // One disparity step d for the lane's pixels a and b: `cur` receives
 // B_R(a - d) (relative pixel 2 lane + e), `prev` holds B_R(b - d).
-template <int NW, bool MASK, bool VOL, bool EDGE>
+template <int NW, int DC, bool MASK, bool VOL, bool EDGE>
 __device__ __forceinline__ void cost_step(const uint64_t *win, int lane, int e, int d,
                                           CostLane<NW> &s, const uint64_t *prev, uint64_t *cur,
                                           int16_t *__restrict__ cost, int H, int W, int v) {
-  load_right<NW>(win, 2 * lane + e, cur);
+  load_right<NW, DC>(win, 2 * lane + e, cur);
   const uint32_t ca = masked_cost(s.bla, s.ma, cur, NW, MASK);
   const uint32_t cb = masked_cost(s.blb, s.mb, prev, NW, MASK);
   const bool va = !EDGE || s.a - d >= 0, vb = !EDGE || s.b - d >= 0;
@@ -510,38 +564,28 @@ __device__ __forceinline__ void cost_step(const uint64_t *win, int lane, int e, 
 
 // All steps d in [dc0, dc1) of one window, two per iteration so that the two
 // register buffers swap roles without copies.
-template <int NW, bool MASK, bool VOL, bool EDGE>
+template <int NW, int DC, bool MASK, bool VOL, bool EDGE>
 __device__ __forceinline__ void cost_chunk(const uint64_t *win, int lane, int dc0, int dc1,
                                            CostLane<NW> &s, int16_t *__restrict__ cost, int H,
                                            int W, int v) {
   uint64_t x[NW], y[NW];
-  load_right<NW>(win, 2 * lane + (dc1 - dc0), x);  // B_R(b - dc0)
+  load_right<NW, DC>(win, 2 * lane + (dc1 - dc0), x);  // B_R(b - dc0)
   int d = dc0;
   for (; d + 1 < dc1; d += 2) {
-    cost_step<NW, MASK, VOL, EDGE>(win, lane, dc1 - 1 - d, d, s, x, y, cost, H, W, v);
-    cost_step<NW, MASK, VOL, EDGE>(win, lane, dc1 - 2 - d, d + 1, s, y, x, cost, H, W, v);
+    cost_step<NW, DC, MASK, VOL, EDGE>(win, lane, dc1 - 1 - d, d, s, x, y, cost, H, W, v);
+    cost_step<NW, DC, MASK, VOL, EDGE>(win, lane, dc1 - 2 - d, d + 1, s, y, x, cost, H, W, v);
   }
-  if (d < dc1) cost_step<NW, MASK, VOL, EDGE>(win, lane, dc1 - 1 - d, d, s, x, y, cost, H, W, v);
+  if (d < dc1) cost_step<NW, DC, MASK, VOL, EDGE>(win, lane, dc1 - 1 - d, d, s, x, y, cost, H, W, v);
 }
 
-template <int NW, bool MASK, bool VOL>
-__global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict__ descL,
-                                                      const uint64_t *__restrict__ maskL,
-                                                      const uint64_t *__restrict__ descR, int W,
-                                                      int H, int dmax, int32_t *__restrict__ disp,
-                                                      int16_t *__restrict__ cost) {
-  extern __shared__ uint64_t win[];
+// One 128-pixel tile of row v starting at u0 (a single wave).
+template <int NW, int DC, bool MASK, bool VOL>
+__device__ __forceinline__ void cost_tile(uint64_t *win, const uint64_t *__restrict__ descL,
+                                          const uint64_t *__restrict__ maskL,
+                                          const uint64_t *__restrict__ descR, int W, int H,
+                                          int dmax, int32_t *__restrict__ disp,
+                                          int16_t *__restrict__ cost, int v, int u0) {
   const int lane = threadIdx.x;
-  // XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin by
-  // id, so ids b, b + 8, b + 16, ... share one XCD and its L2.  Rows are dealt
-  // the same way (row v to XCD v mod 8) and all tiles of a row go to that
-  // XCD, so the row's right descriptors, which every tile of the row reads
-  // with a dmax halo, are fetched from HBM into a single L2.
-  const int tiles = (W + kCostTX - 1) / kCostTX;
-  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const int v = xcd + kXcds * (slot / tiles);
-  if (v >= H) return;  // whole block: ids past the last row of this XCD
-  const int u0 = (slot % tiles) * kCostTX;
   CostLane<NW> s;
   s.a = u0 + 2 * lane;
   s.b = s.a + 1;
@@ -568,27 +612,48 @@ __global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict
   s.best_a = s.best_b = 0xffffffffu;
   const uint64_t *rowR = descR + (size_t)v * W * NW;
 
-  for (int dc0 = 0; dc0 < dmax; dc0 += kCostDC) {
-    const int dc1 = min(dmax, dc0 + kCostDC);
+  for (int dc0 = 0; dc0 < dmax; dc0 += DC) {
+    const int dc1 = min(dmax, dc0 + DC);
     const int r_lo = u0 - dc1 + 1;            // first right pixel of the window
     const int P = kCostTX - 1 + (dc1 - dc0);  // window width
     __syncthreads();                          // previous window fully consumed
-    stage_window<NW>(rowR, r_lo, P, W, lane, win);
+    stage_window<NW, DC>(rowR, r_lo, P, W, lane, win);
     __syncthreads();
     if (u0 < dc1 - 1)  // some a - d < 0 inside this chunk
-      cost_chunk<NW, MASK, VOL, true>(win, lane, dc0, dc1, s, cost, H, W, v);
+      cost_chunk<NW, DC, MASK, VOL, true>(win, lane, dc0, dc1, s, cost, H, W, v);
     else
-      cost_chunk<NW, MASK, VOL, false>(win, lane, dc0, dc1, s, cost, H, W, v);
+      cost_chunk<NW, DC, MASK, VOL, false>(win, lane, dc0, dc1, s, cost, H, W, v);
   }
   if (s.has_a) disp[(size_t)v * W + s.a] = (int32_t)(s.best_a & 0xffffu);
   if (s.has_b) disp[(size_t)v * W + s.b] = (int32_t)(s.best_b & 0xffffu);
 }
 
-// ---------------------------------------------------------------------------
-// K3 (generic): any n = 64 nw bits, nw <= 64.  Lanes over disparities; the
-// left descriptor and mask of the current pixel are wave-uniform (scalar
-// loads); the right descriptors of the window sit in LDS word-major.
-// ---------------------------------------------------------------------------
+template <int NW, int DC, bool MASK, bool VOL>
+__global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict__ descL,
+                                                      const uint64_t *__restrict__ maskL,
+                                                      const uint64_t *__restrict__ descR, int W,
+                                                      int H, int dmax, int32_t *__restrict__ disp,
+                                                      int16_t *__restrict__ cost) {
+  extern __shared__ uint64_t win[];
+  // XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin by
+  // id, so ids b, b + 8, b + 16, ... share one XCD and its L2.  Rows are dealt
+  // the same way (row v to XCD v mod 8) and all tiles of a row go to that
+  // XCD, so the row's right descriptors, which every tile of the row reads
+  // with a dmax halo, are fetched from HBM into a single L2.
+  const int tiles = (W + kCostTX - 1) / kCostTX;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / tiles);
+  if (v >= H) return;  // whole block: ids past the last row of this XCD
+  cost_tile<NW, DC, MASK, VOL>(win, descL, maskL, descR, W, H, dmax, disp, cost, v,
+                               (slot % tiles) * kCostTX);
+}
+
+// ===========================================================================
+// Cost + WTA for any n = 64 nw bits, nw <= 64 (the general fallback).  Lanes
+// over disparities; the left descriptor and mask of the current pixel are
+// wave-uniform (scalar loads); the right descriptors of the window sit in
+// LDS word-major.
+// ===========================================================================
 constexpr int kGenTX = 32;
 constexpr int kGenWin = kGenTX + 63;  // right pixels per window
 
@@ -637,25 +702,196 @@ __global__ __launch_bounds__(64) void k_cost_wta_generic(const uint64_t *__restr
   if (lane < kGenTX && u0 + lane < W) disp[(size_t)v * W + u0 + lane] = (int32_t)(best & 0xffffu);
 }
 
-template <int NW>
-hipError_t launch_describe_mask(const uint32_t *packed, int W, int H, const DeviceTables &t,
-                                uint64_t *desc, uint64_t *mask, hipStream_t s) {
-  const size_t lds = (size_t)(kDescTH + 2 * t.radius) * t.left_pitch * sizeof(uint32_t);
-  dim3 grid((W + kDescTW - 1) / kDescTW, (H + kDescTH - 1) / kDescTH);
-  hipLaunchKernelGGL((k_describe<NW, true>), grid, dim3(kDescThreads), lds, s, packed, W, H,
-                     t.pattern, t.nw, t.radius, t.left_pitch, t.k, desc, mask);
+// ===========================================================================
+// Persistent batch kernels.  Every stage kernel loops: a workgroup takes the
+// next tile index of its queue with one atomic add, finds the pair that owns
+// it (binary search over per-pair prefix sums; pairs are listed largest work
+// first) and runs the same per-tile function as the single-pair kernels.
+// Stages run one after another on the stream, so a stage only reads what the
+// previous stages completed; no workgroup ever waits for another.
+// ===========================================================================
+
+// Largest i in [0, npairs) with start[i] <= t (start[npairs] > t).
+__device__ __forceinline__ int owner(const int *start, int npairs, int t) {
+  int lo = 0, hi = npairs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Next item of a queue for the whole workgroup (broadcast through LDS).
+__device__ __forceinline__ int take(int *counter, int *slot) {
+  __syncthreads();  // everyone has read the previous value
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  return *slot;
+}
+
+__global__ void k_batch_reset(int *counters) {
+  if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *__restrict__ bw,
+                                                               const uint16_t *__restrict__ lin,
+                                                               const uint16_t *__restrict__ ftab,
+                                                               Mq mq, int use_mask) {
+  __shared__ int slot;
+  const int *start = bw->start + kQueueColor * (bw->npairs + 1);
+  const int total = start[bw->npairs];
+  for (;;) {
+    const int t = take(bw->counters + kQueueColor, &slot);
+    if (t >= total) break;
+    const int i = owner(start, bw->npairs, t);
+    const BatchPair &p = bw->pairs[bw->order[i]];
+    const int tx = (p.W + kColorTX - 1) / kColorTX, ty = (p.H + kColorTY - 1) / kColorTY;
+    const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
+    color_tile(view ? p.right : p.left, p.W, p.H, p.stride, view ? p.packedR : p.packedL, lin,
+               ftab, mq, view == 0 && use_mask, (tile % tx) * kColorTX, (tile / tx) * kColorTY);
+  }
+}
+
+template <int NW, int TW>
+__global__ __launch_bounds__(kDescThreads) void k_batch_describe_mask(
+    const BatchWork *__restrict__ bw, DescribeConsts c) {
+  extern __shared__ uint32_t tile[];
+  __shared__ int slot;
+  const int *start = bw->start + kQueueDescribeMask * (bw->npairs + 1);
+  const int total = start[bw->npairs];
+  for (;;) {
+    const int t = take(bw->counters + kQueueDescribeMask, &slot);
+    if (t >= total) break;
+    const int i = owner(start, bw->npairs, t);
+    const BatchPair &p = bw->pairs[bw->order[i]];
+    const int tx = (p.W + TW - 1) / TW;
+    const int local = t - start[i];
+    describe_mask_tile<NW, TW>(tile, p.packedL, p.W, p.H, c, p.descL, p.maskL,
+                               (local % tx) * TW, (local / tx) * kDescTH);
+  }
+}
+
+// Descriptor-only tiles: the right view of every pair, plus the left view
+// when the mask is off.
+__global__ __launch_bounds__(kRightThreads) void k_batch_describe_right(
+    const BatchWork *__restrict__ bw, RightConsts c) {
+  extern __shared__ int2 lds_offs[];
+  __shared__ int slot;
+  stage_right_offsets(lds_offs, c);
+  const int *start = bw->start + kQueueDescribe * (bw->npairs + 1);
+  const int total = start[bw->npairs];
+  for (;;) {
+    const int t = take(bw->counters + kQueueDescribe, &slot);
+    if (t >= total) break;
+    const int i = owner(start, bw->npairs, t);
+    const BatchPair &p = bw->pairs[bw->order[i]];
+    const int tx = (p.W + kRightTW - 1) / kRightTW, ty = (p.H + kRightTH - 1) / kRightTH;
+    const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
+    // view 0 is the right view; view 1 (mask off only) the left view
+    describe_right_tile(lds_offs, view ? p.packedL : p.packedR, p.W, p.H, c,
+                        view ? p.descL : p.descR, (tile % tx) * kRightTW,
+                        (tile / tx) * kRightTH);
+  }
+}
+
+// Next item of a queue for a one-wave workgroup: lane 0 adds, every lane
+// reads the result.
+__device__ __forceinline__ int wave_take(int *counter) {
+  int t = 0;
+  if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+// Cost tiles.  Queue x (one per XCD) holds the tiles of the rows v = x mod 8
+// of every pair; a workgroup serves the queue of its own XCD first (so a
+// row's tiles share one L2) and then helps the others.  Pairs with and
+// without a cost volume have their own queues and kernels.  The next item is
+// claimed before the current tile runs, so the atomic's latency is hidden,
+// and the owning pair is looked up again only when an item leaves it.
+template <int NW, int DC, bool MASK, bool VOL>
+__global__ __launch_bounds__(64) void k_batch_cost(const BatchWork *__restrict__ bw) {
+  extern __shared__ uint64_t win[];
+  const int home = blockIdx.x % kXcds;
+  const int n = bw->npairs;
+  for (int qi = 0; qi < kXcds; ++qi) {
+    const int x = (home + qi) % kXcds;
+    const int q = (VOL ? kQueueCostVol0 : kQueueCost0) + x;
+    const int *start = bw->start + q * (n + 1);
+    const int total = start[n];
+    int *counter = bw->counters + q;
+    int cur = wave_take(counter);
+    int i = 0, i_end = -1;  // pair of the last item and the end of its range
+    while (cur < total) {
+      const int next = wave_take(counter);
+      if (cur >= i_end || cur < start[i]) {
+        i = owner(start, n, cur);
+        i_end = start[i + 1];
+      }
+      const BatchPair &p = bw->pairs[bw->order[i]];
+      const int tiles = (p.W + kCostTX - 1) / kCostTX;
+      const int local = cur - start[i];
+      cost_tile<NW, DC, MASK, VOL>(win, p.descL, p.maskL, p.descR, p.W, p.H, p.dmax, p.disp,
+                                   p.cost, x + kXcds * (local / tiles),
+                                   (local % tiles) * kCostTX);
+      cur = next;
+    }
+  }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+DescribeConsts describe_consts(const DeviceTables &t) {
+  return DescribeConsts{t.pattern, t.nw, t.radius, t.left_pitch_for(t.tune.desc_tile_w), t.k};
+}
+
+RightConsts right_consts(const DeviceTables &t) {
+  return RightConsts{t.right_offs, t.n, t.nw, t.radius, t.right_pitch};
+}
+
+size_t mask_lds_bytes(const DeviceTables &t, int tw) {
+  return (size_t)(kDescTH + 2 * t.radius) * t.left_pitch_for(tw) * sizeof(uint32_t);
+}
+
+template <int NW, int TW>
+hipError_t launch_describe_mask_t(const uint32_t *packed, int W, int H, const DeviceTables &t,
+                                  uint64_t *desc, uint64_t *mask, hipStream_t s) {
+  DescribeConsts c = describe_consts(t);
+  c.pitch = t.left_pitch_for(TW);
+  dim3 grid((W + TW - 1) / TW, (H + kDescTH - 1) / kDescTH);
+  hipLaunchKernelGGL((k_describe_mask<NW, TW>), grid, dim3(kDescThreads), mask_lds_bytes(t, TW), s,
+                     packed, W, H, c, desc, mask);
   return hipGetLastError();
 }
 
 template <int NW>
-hipError_t launch_cost_fast(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
-                            int W, int H, int dmax, int32_t *disp, int16_t *cost, hipStream_t s) {
+hipError_t launch_describe_mask_nw(const uint32_t *packed, int W, int H, const DeviceTables &t,
+                                   uint64_t *desc, uint64_t *mask, hipStream_t s) {
+  return t.tune.desc_tile_w == 32
+             ? launch_describe_mask_t<NW, 32>(packed, W, H, t, desc, mask, s)
+             : launch_describe_mask_t<NW, 16>(packed, W, H, t, desc, mask, s);
+}
+
+// Raises a kernel's dynamic LDS limit above the 64 KiB default.  The describe
+// kernels need at most ~75 KiB (n = 4096, S = 63); 128 KiB leaves room for the
+// kernels' static LDS within the 160 KiB of a workgroup.
+hipError_t allow_big_lds(const void *kernel) {
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+}
+
+template <int NW, int DC>
+hipError_t launch_cost_fast_dc(const uint64_t *descL, const uint64_t *maskL,
+                               const uint64_t *descR, int W, int H, int dmax, int32_t *disp,
+                               int16_t *cost, hipStream_t s) {
   const int tiles = (W + kCostTX - 1) / kCostTX;
   dim3 grid(kXcds * tiles * ((H + kXcds - 1) / kXcds));
-  const size_t lds = (size_t)NW * 2 * kCostHP * sizeof(uint64_t);
-#define BSM_LAUNCH_COST(M, V)                                                                     \
-  hipLaunchKernelGGL((k_cost_wta_fast<NW, M, V>), grid, dim3(64), lds, s, descL, maskL, descR, W, \
-                     H, dmax, disp, cost)
+  const size_t lds = Window<NW, DC>::kBytes;
+#define BSM_LAUNCH_COST(M, V)                                                                  \
+  hipLaunchKernelGGL((k_cost_wta_fast<NW, DC, M, V>), grid, dim3(64), lds, s, descL, maskL, \
+                     descR, W, H, dmax, disp, cost)
   if (maskL) {
     if (cost) BSM_LAUNCH_COST(true, true);
     else BSM_LAUNCH_COST(true, false);
@@ -667,50 +903,150 @@ hipError_t launch_cost_fast(const uint64_t *descL, const uint64_t *maskL, const 
   return hipGetLastError();
 }
 
+template <int NW>
+hipError_t launch_cost_fast(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
+                            int W, int H, int dmax, int32_t *disp, int16_t *cost, int dc,
+                            hipStream_t s) {
+  return dc == 32 ? launch_cost_fast_dc<NW, 32>(descL, maskL, descR, W, H, dmax, disp, cost, s)
+                  : launch_cost_fast_dc<NW, 64>(descL, maskL, descR, W, H, dmax, disp, cost, s);
+}
+
+// Persistent grid: `per_cu` workgroups per CU (0: as many as fit), rounded
+// to a multiple of the XCD count.
+template <typename K>
+int persistent_grid(K kernel, int threads, size_t lds, int per_cu) {
+  int dev = 0, cus = 0, fit = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void *>(kernel),
+                                                     threads, lds);
+  if (cus < 1) cus = 256;
+  if (fit < 1) fit = 1;
+  const int k = per_cu > 0 ? std::min(per_cu, fit) : fit;
+  return std::max(kXcds, (cus * k + kXcds - 1) / kXcds * kXcds);
+}
+
+template <int NW, int TW, int DC>
+hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
+                          hipStream_t s) {
+  const Tuning &tu = t.tune;
+  const BatchWork *bw = bl.work;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bl.counters);
+  const int g0 = persistent_grid(k_batch_color, kColorThreads, 0, tu.blocks_per_cu[0]);
+  hipLaunchKernelGGL(k_batch_color, dim3(g0), dim3(kColorThreads), 0, s, bw, t.lin, t.f,
+                     t.mq, use_mask);
+  if (use_mask) {
+    DescribeConsts c = describe_consts(t);
+    c.pitch = t.left_pitch_for(TW);
+    const size_t lds = mask_lds_bytes(t, TW);
+    const int g1 = persistent_grid(k_batch_describe_mask<NW, TW>, kDescThreads, lds,
+                                   tu.blocks_per_cu[1]);
+    hipLaunchKernelGGL((k_batch_describe_mask<NW, TW>), dim3(g1), dim3(kDescThreads), lds, s,
+                       bw, c);
+  }
+  {
+    static const hipError_t attr = allow_big_lds(reinterpret_cast<const void *>(k_batch_describe_right));
+    if (attr != hipSuccess) return attr;
+    const size_t lds = right_lds_bytes(t.n, t.radius, t.right_pitch);
+    const int g2 = persistent_grid(k_batch_describe_right, kRightThreads, lds, tu.blocks_per_cu[2]);
+    hipLaunchKernelGGL(k_batch_describe_right, dim3(g2), dim3(kRightThreads), lds, s, bw,
+                       right_consts(t));
+  }
+  {
+    // pairs without a volume, then pairs with one (each kernel's queues are
+    // empty when the batch has no pair of its kind)
+    const size_t lds = Window<NW, DC>::kBytes;
+#define BSM_LAUNCH_BATCH_COST(M, V)                                                          \
+  do {                                                                                       \
+    const int g3 = persistent_grid(k_batch_cost<NW, DC, M, V>, 64, lds, tu.blocks_per_cu[3]); \
+    hipLaunchKernelGGL((k_batch_cost<NW, DC, M, V>), dim3(g3), dim3(64), lds, s, bw);        \
+  } while (0)
+    if (use_mask) {
+      BSM_LAUNCH_BATCH_COST(true, false);
+      BSM_LAUNCH_BATCH_COST(true, true);
+    } else {
+      BSM_LAUNCH_BATCH_COST(false, false);
+      BSM_LAUNCH_BATCH_COST(false, true);
+    }
+#undef BSM_LAUNCH_BATCH_COST
+  }
+  return hipGetLastError();
+}
+
+template <int NW, int TW>
+hipError_t launch_batch_tw(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
+                           hipStream_t s) {
+  return t.tune.cost_dchunk == 32 ? launch_batch_t<NW, TW, 32>(bl, t, use_mask, s)
+                                  : launch_batch_t<NW, TW, 64>(bl, t, use_mask, s);
+}
+
+template <int NW>
+hipError_t launch_batch_nw(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
+                           hipStream_t s) {
+  return t.tune.desc_tile_w == 32 ? launch_batch_tw<NW, 32>(bl, t, use_mask, s)
+                                  : launch_batch_tw<NW, 16>(bl, t, use_mask, s);
+}
+
 }  // namespace
 
-int describe_left_cols(int radius) { return kDescTW + 2 * radius; }
+int describe_left_cols(int radius, int tile_w) { return tile_w + 2 * radius; }
 int describe_right_cols(int radius) { return kRightTW + 2 * radius; }
+
+void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
+                       int counts[kBatchQueues]) {
+  counts[kQueueColor] = 2 * ((W + kColorTX - 1) / kColorTX) * ((H + kColorTY - 1) / kColorTY);
+  counts[kQueueDescribeMask] =
+      use_mask ? ((W + desc_tile_w - 1) / desc_tile_w) * ((H + kDescTH - 1) / kDescTH) : 0;
+  counts[kQueueDescribe] =
+      (use_mask ? 1 : 2) * ((W + kRightTW - 1) / kRightTW) * ((H + kRightTH - 1) / kRightTH);
+  const int tiles = (W + kCostTX - 1) / kCostTX;
+  for (int x = 0; x < kXcds; ++x) {
+    const int rows_tiles = H > x ? tiles * ((H - x + kXcds - 1) / kXcds) : 0;
+    counts[kQueueCost0 + x] = want_cost ? 0 : rows_tiles;
+    counts[kQueueCostVol0 + x] = want_cost ? rows_tiles : 0;
+  }
+}
+
+bool batch_supported(int nw) { return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16; }
 
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride, uint32_t *packed,
                         int want_lab, const DeviceTables &t, hipStream_t s) {
   dim3 grid((W + kColorTX - 1) / kColorTX, (H + kColorTY - 1) / kColorTY);
-  hipLaunchKernelGGL(k_color, grid, dim3(kColorTX * kColorTY), 0, s, img, W, H, stride, packed,
-                     t.lin, t.f, t.mq, want_lab);
+  hipLaunchKernelGGL(k_color, grid, dim3(kColorThreads), 0, s, img, W, H, stride, packed, t.lin,
+                     t.f, t.mq, want_lab);
   return hipGetLastError();
 }
 
 hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTables &t,
                            uint64_t *desc, uint64_t *mask, hipStream_t s) {
   if (!mask) {
-    const size_t lds = right_lds_bytes(t.n, t.radius, t.right_pitch);
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(k_describe_right),
-        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static const hipError_t attr = allow_big_lds(reinterpret_cast<const void *>(k_describe_right));
     if (attr != hipSuccess) return attr;
+    const size_t lds = right_lds_bytes(t.n, t.radius, t.right_pitch);
     dim3 grid((W + kRightTW - 1) / kRightTW, (H + kRightTH - 1) / kRightTH);
     hipLaunchKernelGGL(k_describe_right, grid, dim3(kRightThreads), lds, s, packed, W, H,
-                       t.right_offs, t.nw, t.radius, t.right_pitch, desc);
+                       right_consts(t), desc);
     return hipGetLastError();
   }
-  if (t.nw <= 1) return launch_describe_mask<1>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 2) return launch_describe_mask<2>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 4) return launch_describe_mask<4>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 8) return launch_describe_mask<8>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 16) return launch_describe_mask<16>(packed, W, H, t, desc, mask, s);
-  if (t.nw <= 32) return launch_describe_mask<32>(packed, W, H, t, desc, mask, s);
-  return launch_describe_mask<64>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 1) return launch_describe_mask_nw<1>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 2) return launch_describe_mask_nw<2>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 4) return launch_describe_mask_nw<4>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 8) return launch_describe_mask_nw<8>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 16) return launch_describe_mask_nw<16>(packed, W, H, t, desc, mask, s);
+  if (t.nw <= 32) return launch_describe_mask_nw<32>(packed, W, H, t, desc, mask, s);
+  return launch_describe_mask_nw<64>(packed, W, H, t, desc, mask, s);
 }
 
 hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
                            int W, int H, int nw, int dmax, int32_t *disp, int16_t *cost,
-                           hipStream_t s) {
+                           const DeviceTables &t, hipStream_t s) {
+  const int dc = t.tune.cost_dchunk;
   switch (nw) {
-    case 1: return launch_cost_fast<1>(descL, maskL, descR, W, H, dmax, disp, cost, s);
-    case 2: return launch_cost_fast<2>(descL, maskL, descR, W, H, dmax, disp, cost, s);
-    case 4: return launch_cost_fast<4>(descL, maskL, descR, W, H, dmax, disp, cost, s);
-    case 8: return launch_cost_fast<8>(descL, maskL, descR, W, H, dmax, disp, cost, s);
-    case 16: return launch_cost_fast<16>(descL, maskL, descR, W, H, dmax, disp, cost, s);
+    case 1: return launch_cost_fast<1>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
+    case 2: return launch_cost_fast<2>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
+    case 4: return launch_cost_fast<4>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
+    case 8: return launch_cost_fast<8>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
+    case 16: return launch_cost_fast<16>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
     default: break;
   }
   dim3 grid((W + kGenTX - 1) / kGenTX, H);
@@ -718,6 +1054,18 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const u
   hipLaunchKernelGGL(k_cost_wta_generic, grid, dim3(64), lds, s, descL, maskL, descR, W, H, nw,
                      dmax, disp, cost);
   return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
+                        hipStream_t s) {
+  switch (t.nw) {
+    case 1: return launch_batch_nw<1>(bl, t, use_mask, s);
+    case 2: return launch_batch_nw<2>(bl, t, use_mask, s);
+    case 4: return launch_batch_nw<4>(bl, t, use_mask, s);
+    case 8: return launch_batch_nw<8>(bl, t, use_mask, s);
+    case 16: return launch_batch_nw<16>(bl, t, use_mask, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace bsm

@@ -1,0 +1,174 @@
+"""GPU tests of the batched path (bsm_match_batch), the launch tunings and
+the autotuner.  Every result is compared bit for bit with the CPU oracle or
+with the single-pair path (itself checked against the oracle)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1402_2020_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bsm():
+    from paper_1402_2020_amd import _bsm
+    _bsm.load()
+    return _bsm
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _ctx(bsm, orc, n, S, use_mask=True, seed=7):
+    sigma = 4.0 * S / 26
+    pat = orc.make_pattern(seed, n, S, sigma)
+    return bsm.Context(n, S, sigma, pattern=pat, use_mask=use_mask), pat
+
+
+def _scenes(count, scale, first=0):
+    return [synth.batch_scene(s, scale=scale) for s in synth.batch_specs(first + count)[first:]]
+
+
+def _check_batch_vs_oracle(torch, ctx, pat, orc, scenes, want_cost, use_mask=True):
+    items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
+    outs = ctx.match_batch(items, want_cost=want_cost)
+    torch.cuda.synchronize()
+    orc.set_threads(8)
+    try:
+        for s, (disp, cost) in zip(scenes, outs):
+            wd, wc = orc.match(s.left, s.right, pat, s.dmax, use_mask=use_mask,
+                               want_cost=want_cost)
+            assert np.array_equal(disp.cpu().numpy(), wd), (s.left.shape, s.dmax)
+            if want_cost:
+                assert np.array_equal(cost.cpu().numpy(), wc)
+    finally:
+        orc.set_threads(1)
+    return outs
+
+
+@pytest.mark.parametrize("n,S,scale,want_cost", [(256, 15, 0.15, True), (1024, 31, 0.12, False),
+                                                 (64, 7, 0.1, True), (512, 31, 0.1, False)])
+def test_batch_persistent_equals_oracle(torch_cuda, bsm, orc, n, S, scale, want_cost):
+    _say(f"case: persistent batch n={n} S={S} scale={scale} volume={want_cost}")
+    ctx, pat = _ctx(bsm, orc, n, S)
+    _check_batch_vs_oracle(torch_cuda, ctx, pat, orc, _scenes(7, scale), want_cost)
+    ctx.close()
+
+
+def test_batch_without_mask(torch_cuda, bsm, orc):
+    _say("case: persistent batch, mask off (Eq. 4)")
+    ctx, pat = _ctx(bsm, orc, 256, 15, use_mask=False)
+    _check_batch_vs_oracle(torch_cuda, ctx, pat, orc, _scenes(5, 0.12), True, use_mask=False)
+    ctx.close()
+
+
+def test_batch_sequential_fallback(torch_cuda, bsm, orc):
+    _say("case: batch with n=192 (runs pair by pair)")
+    ctx, pat = _ctx(bsm, orc, 192, 11)
+    _check_batch_vs_oracle(torch_cuda, ctx, pat, orc, _scenes(3, 0.1), True)
+    ctx.close()
+
+
+def test_batch_graph_reused_across_shapes_and_replays(torch_cuda, bsm, orc):
+    torch = torch_cuda
+    _say("case: batch graph replays with different shapes and eager work between")
+    ctx, pat = _ctx(bsm, orc, 256, 15)
+    first = _scenes(4, 0.1)
+    second = _scenes(6, 0.13, first=10)
+    want = {}
+    for s in first + second:
+        want[id(s)] = orc.match(s.left, s.right, pat, s.dmax)[0]
+    for rep in range(3):
+        for group in (first, second):
+            items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in group]
+            outs = ctx.match_batch(items)
+            # eager work of the program between replays
+            junk = torch.randn(1000, device="cuda").sum()
+            torch.cuda.synchronize()
+            for s, (disp, _) in zip(group, outs):
+                assert np.array_equal(disp.cpu().numpy(), want[id(s)]), rep
+            del junk
+    ctx.close()
+
+
+def test_batch_equals_single_pair_path_full_size(torch_cuda, bsm, orc):
+    torch = torch_cuda
+    _say("case: batch of 6 full-size uneven pairs == single-pair path")
+    ctx, pat = _ctx(bsm, orc, 1024, 31, seed=synth.PATTERN_SEED)
+    scenes = _scenes(6, 1.0)
+    items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
+    outs = ctx.match_batch(items)
+    singles = [ctx.match(L, R, d)[0] for L, R, d in items]
+    torch.cuda.synchronize()
+    for (disp, _), single in zip(outs, singles):
+        assert torch.equal(disp, single)
+    # and one of them against the oracle (smallest, to bound CPU time)
+    k = min(range(len(scenes)), key=lambda i: scenes[i].left.size * scenes[i].dmax)
+    orc.set_threads(16)
+    wd, _ = orc.match(scenes[k].left, scenes[k].right, pat, scenes[k].dmax)
+    orc.set_threads(1)
+    assert np.array_equal(outs[k][0].cpu().numpy(), wd)
+    ctx.close()
+
+
+TUNINGS = [dict(desc_tile_w=tw, cost_dchunk=dc, blocks_per_cu=[0, bm, 0, bc])
+           for tw in (16, 32) for dc in (32, 64) for bm, bc in ((0, 0), (2, 1))]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"tw{t['desc_tile_w']}-dc{t['cost_dchunk']}-"
+                         f"b{t['blocks_per_cu'][1]}{t['blocks_per_cu'][3]}")
+def test_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
+    torch = torch_cuda
+    _say(f"case: tuning {tuning}")
+    ctx, pat = _ctx(bsm, orc, 1024, 31, seed=11)
+    sc = synth.slanted_scene(33, 300, 70, 130)
+    ctx.set_tuning(tuning)
+    assert ctx.tuning() == tuning
+    L, R = _dev(torch, sc.left), _dev(torch, sc.right)
+    disp, cost = ctx.match(L, R, sc.dmax, want_cost=True)
+    outs = ctx.match_batch([(L, R, sc.dmax)], want_cost=True)
+    torch.cuda.synchronize()
+    wd, wc = orc.match(sc.left, sc.right, pat, sc.dmax, want_cost=True)
+    assert np.array_equal(disp.cpu().numpy(), wd)
+    assert np.array_equal(cost.cpu().numpy(), wc)
+    assert np.array_equal(outs[0][0].cpu().numpy(), wd)
+    assert np.array_equal(outs[0][1].cpu().numpy(), wc)
+    ctx.close()
+
+
+def test_set_tuning_validates(torch_cuda, bsm, orc):
+    ctx, _ = _ctx(bsm, orc, 256, 15)
+    for bad in (dict(desc_tile_w=8, cost_dchunk=64), dict(desc_tile_w=16, cost_dchunk=48),
+                dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 65])):
+        assert bsm.bsm_set_tuning(ctx.h, bsm.Tuning.from_dict(bad)) == bsm.EINVAL
+    ctx.close()
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(torch_cuda, bsm, orc):
+    torch = torch_cuda
+    _say("case: autotune on a small uneven batch")
+    ctx, pat = _ctx(bsm, orc, 256, 15)
+    scenes = _scenes(4, 0.15)
+    items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
+    best, ms = ctx.autotune(items, reps=2)
+    assert best in TUNINGS or best["desc_tile_w"] in (16, 32)
+    assert ms > 0
+    assert ctx.tuning() == best
+    _check_batch_vs_oracle(torch, ctx, pat, orc, scenes, False)
+    ctx.close()
