@@ -32,6 +32,7 @@ WORKLOADS = {
     1: "450x375 slanted planes, dmax 60, n 1024, S 31, int16 cost volume",
     2: "1400x1100 slanted planes + radiometric change, dmax 256, n 1024, S 31",
     3: "64 uneven slanted-plane pairs (W 320-1920, H 240-1080, dmax 32-256), n 1024, S 31",
+    4: "serving: Poisson arrivals of the 64 uneven pairs, n 1024, S 31, 32 GiB admission cap",
 }
 
 
@@ -117,6 +118,137 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _percentiles(lat):
+    import numpy as np
+    a = np.asarray(lat) * 1e3
+    return {"p50_ms": round(float(np.percentile(a, 50)), 3),
+            "p99_ms": round(float(np.percentile(a, 99)), 3),
+            "max_ms": round(float(a.max()), 3)}
+
+
+def bench_serve(args):
+    """Serving: for each arrival rate, a Poisson stream of pairs drawn from
+    the 64 uneven pairs is submitted at its scheduled times (host buffers in,
+    host buffers out, admission capped at 32 GiB of device working set), and
+    the same stream is replayed through a one-at-a-time loop (copy in,
+    bsm_match, copy out, wait).  Latency is measured from each pair's
+    scheduled arrival to its result being in host memory."""
+    import numpy as np
+    import torch
+
+    from paper_1402_2020_amd import _bsm, synth
+    n, S = 1024, 31
+    sigma = 4.0 * S / 26
+    specs = synth.batch_specs(64)
+    t0 = time.perf_counter()
+    scenes = [synth.batch_scene(s) for s in specs]
+    gen_s = time.perf_counter() - t0
+    pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
+    ctx = _bsm.Context(n, S, sigma, pattern=pat, device=0)
+    ctx.serve_config(32 << 30, 1 << 16)
+    dev = torch.device("cuda:0")
+    first = {}
+
+    def note(j, disp):
+        if j in first:
+            return bool(np.array_equal(first[j], disp))
+        first[j] = disp.copy()
+        return True
+
+    # warm-up: every slot's batch state and graph, the memory pool
+    for _ in range(2):
+        ts = [ctx.submit(s.left, s.right, s.dmax) for s in scenes[:16]]
+        ctx.drain()
+        for j, t in enumerate(ts):
+            state, _, res = ctx.poll(t)
+            if state != 1:
+                raise RuntimeError(f"served warm-up pair {j} failed")
+            note(j, res[0])
+    for s in scenes[:4]:
+        ctx.match(torch.from_numpy(s.left).to(dev), torch.from_numpy(s.right).to(dev), s.dmax)
+    torch.cuda.synchronize()
+
+    same = True
+    rates = {}
+    for rate in args.rates:
+        arr, items = synth.poisson_arrivals(rate, args.duration, len(scenes), seed=1402 + rate)
+        # served
+        lat, ends, pending = [], [], []
+        start = time.monotonic() + 0.05
+        i = 0
+        while i < len(arr) or pending:
+            now = time.monotonic()
+            if i < len(arr) and now >= start + arr[i]:
+                s = scenes[items[i]]
+                pending.append((ctx.submit(s.left, s.right, s.dmax), i))
+                i += 1
+                continue
+            while pending:
+                state, times, out = ctx.poll(pending[0][0])
+                if state == 0:
+                    break
+                if state != 1:
+                    raise RuntimeError("served pair failed")
+                k = pending.pop(0)[1]
+                lat.append(times[3] - (start + arr[k]))
+                ends.append(times[3])
+                if k < 256:
+                    same &= note(int(items[k]), out[0])
+            if i < len(arr):
+                time.sleep(max(0.0, min(2e-4, start + arr[i] - time.monotonic())))
+            elif pending:
+                time.sleep(2e-4)
+        served_s = max(ends) - start
+        served = {"pairs": len(arr), "pairs_per_s": round(len(arr) / served_s, 2),
+                  "span_s": round(served_s, 3), **_percentiles(lat)}
+        print(json.dumps({"progress": "served", "rate": rate, **served}), flush=True)
+        # one at a time
+        lat = []
+        start = time.monotonic() + 0.05
+        for k in range(len(arr)):
+            wait = start + arr[k] - time.monotonic()
+            if wait > 0:
+                time.sleep(wait)
+            s = scenes[items[k]]
+            L = torch.from_numpy(s.left).to(dev)
+            R = torch.from_numpy(s.right).to(dev)
+            d, _ = ctx.match(L, R, s.dmax)
+            out = d.cpu().numpy()
+            lat.append(time.monotonic() - (start + arr[k]))
+            if k < 64:
+                same &= note(int(items[k]), out)
+        plain_s = time.monotonic() - start
+        plain = {"pairs": len(arr), "pairs_per_s": round(len(arr) / plain_s, 2),
+                 "span_s": round(plain_s, 3), **_percentiles(lat)}
+        print(json.dumps({"progress": "plain", "rate": rate, **plain}), flush=True)
+        rates[str(rate)] = {"served": served, "plain": plain}
+
+    top = rates[str(max(args.rates))]
+    out = {
+        "metric": "pairs/sec served (p50/p99 latency beside)",
+        "value": top["served"]["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": sum(v["served"]["pairs"] for v in rates.values()),
+        "warmup": 32,
+        "ms_per_step": 1e3 / top["served"]["pairs_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded scene generator; Middlebury stand-in)",
+        "config": {"workload": WORKLOADS[4], "rates_per_s": list(args.rates),
+                   "duration_s": args.duration, "n_bits": n, "window": S,
+                   "admission_cap_bytes": 32 << 30},
+        "rates": rates,
+        "results_identical": bool(same),
+        "scene_generation_s": round(gen_s, 2),
+        "roofline": None,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources_hash():
     h = hashlib.sha256()
     for name in ("bsm_kernels.hip",):
@@ -162,6 +294,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--duration", type=float, default=60.0,
+                    help="serving workload: seconds of arrivals per rate")
+    ap.add_argument("--rates", type=int, nargs="+", default=[50, 200, 800],
+                    help="serving workload: arrival rates, pairs/s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (5 times), to scale "
                          "the HBM byte counters of a profiler run")
@@ -192,6 +328,8 @@ def main():
     cfg = args.config
     if cfg == 3:
         return bench_batch(args)
+    if cfg == 4:
+        return bench_serve(args)
     p = synth.CONFIG_PARAMS[cfg]
     scene = synth.config_scene(cfg)
     H, W = scene.left.shape[:2]

@@ -354,3 +354,43 @@ class Context:
         pairs, outs, keep = self._pairs(items, want_cost)
         _check(bsm_match_batch(self.h, pairs, _stream(stream)), "bsm_match_batch")
         return outs
+
+    # ---- serving (host buffers) -------------------------------------------
+
+    def serve_config(self, cap_bytes, max_queue):
+        _check(bsm_serve_config(self.h, cap_bytes, max_queue), "bsm_serve_config")
+
+    def submit(self, left, right, dmax, want_cost=False):
+        """Queues one pair of uint8 host arrays [H][W][3] (numpy); returns a
+        ticket.  The arrays and the result buffers stay referenced here until
+        the ticket is reported done or failed by poll()."""
+        import numpy as np
+        if not hasattr(self, "_serving"):
+            self._serving = {}
+        L = np.ascontiguousarray(left, dtype=np.uint8)
+        R = np.ascontiguousarray(right, dtype=np.uint8)
+        if L.ndim != 3 or L.shape[2] != 3 or R.shape != L.shape:
+            raise ValueError("left and right must be uint8 arrays of the same shape [H][W][3]")
+        H, W, _ = L.shape
+        disp = np.empty((H, W), np.int32)
+        cost = np.empty((dmax, H, W), np.int16) if want_cost else None
+        pair = Pair(L.ctypes.data, R.ctypes.data, W, H, 3 * W, dmax, disp.ctypes.data,
+                    None if cost is None else cost.ctypes.data)
+        st, ticket = bsm_submit(self.h, pair)
+        _check(st, "bsm_submit")
+        self._serving[ticket] = (L, R, disp, cost)
+        return ticket
+
+    def poll(self, ticket):
+        """Returns (state, times, (disp, cost) or None): state 0 pending,
+        1 done, -1 failed; times = (arrive, admit, start, end) seconds."""
+        st, state, t = bsm_poll(self.h, ticket)
+        _check(st, "bsm_poll")
+        times = (t.t_arrive, t.t_admit, t.t_start, t.t_end)
+        if state == 0:
+            return state, times, None
+        _, _, disp, cost = self._serving.pop(ticket)
+        return state, times, ((disp, cost) if state == 1 else None)
+
+    def drain(self):
+        _check(bsm_drain(self.h), "bsm_drain")

@@ -21,9 +21,15 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct BatchState {
   Scratch scratch;               // per-pair planes and descriptors
-  BatchWork *d_work = nullptr;   // fixed device address, captured in the graph
-  char *d_tables = nullptr;      // pairs | order | start | counters
+  // d_work and d_counters live in one allocation at a fixed device address:
+  // both are baked into the captured graph, so neither may move while the
+  // graph exists.  The tables (which grow with the batch) are only reached
+  // through d_work.
+  BatchWork *d_work = nullptr;
+  int *d_counters = nullptr;     // [kBatchQueues] queue heads
+  char *d_tables = nullptr;      // pairs | order | start
   size_t d_tables_cap = 0;
+  Tuning tune;                   // launch choices the graph was captured with
   char *h_stage = nullptr;       // pinned staging of BatchWork + tables
   size_t h_stage_cap = 0;
   hipEvent_t done = nullptr;     // last batch finished with the tables
@@ -54,13 +60,6 @@ struct BatchState {
 
 void batch_state_free(BatchState *b) { delete b; }
 
-void batch_invalidate(bsm_ctx *ctx) {
-  if (ctx && ctx->batch) {
-    if (ctx->batch->launched) (void)hipEventSynchronize(ctx->batch->done);
-    ctx->batch->drop_graph();
-  }
-}
-
 namespace {
 
 // Scratch bytes of one pair in a batch: both colour planes, descriptors of
@@ -69,6 +68,23 @@ size_t pair_scratch_bytes(const bsm_ctx *ctx, int W, int H) {
   const size_t px = (size_t)W * H;
   return 2 * align_up(px * 4, 256) + 3 * align_up(px * ctx->nw * 8, 256);
 }
+
+}  // namespace
+
+bsm_status batch_state_create(bsm_ctx *ctx, BatchState **out) {
+  std::unique_ptr<BatchState> b(new BatchState);
+  hipError_t e;
+  const size_t work_bytes = align_up(sizeof(BatchWork), 256);
+  if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipMalloc(&b->d_work, work_bytes + kBatchQueues * sizeof(int))) != hipSuccess)
+    return device_fail(ctx, e, "batch state");
+  b->d_counters = reinterpret_cast<int *>(reinterpret_cast<char *>(b->d_work) + work_bytes);
+  *out = b.release();
+  return BSM_OK;
+}
+
+namespace {
 
 bsm_status validate_pairs(const bsm_pair *pairs, int npairs) {
   if (npairs < 0 || (npairs > 0 && !pairs)) return fail(BSM_EINVAL, "invalid pair list");
@@ -87,12 +103,13 @@ bsm_status validate_pairs(const bsm_pair *pairs, int npairs) {
 }
 
 // Pairs one after another (n outside the batch kernels' range).
-bsm_status batch_sequential(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hipStream_t s) {
+bsm_status batch_sequential(bsm_ctx *ctx, BatchState &b, const bsm_pair *pairs, int npairs,
+                            hipStream_t s) {
   size_t need = 0;
   for (int i = 0; i < npairs; ++i)
     need = std::max(need, match_scratch_bytes(ctx, pairs[i].width, pairs[i].height));
   hipError_t e;
-  void *buf = ctx->batch->scratch.acquire(need, s, &e);
+  void *buf = b.scratch.acquire(need, s, &e);
   if (!buf) return device_fail(ctx, e, "batch scratch");
   for (int i = 0; i < npairs; ++i) {
     const bsm_pair &p = pairs[i];
@@ -100,13 +117,20 @@ bsm_status batch_sequential(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hip
                                     p.disp, p.cost, buf, s);
     if (st != BSM_OK) return st;
   }
-  if ((e = ctx->batch->scratch.release(s)) != hipSuccess)
+  if ((e = b.scratch.release(s)) != hipSuccess)
     return device_fail(ctx, e, "batch scratch event");
   return BSM_OK;
 }
 
-bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hipStream_t s) {
-  BatchState &b = *ctx->batch;
+bool same_tuning(const Tuning &a, const Tuning &b) {
+  if (a.desc_tile_w != b.desc_tile_w || a.cost_dchunk != b.cost_dchunk) return false;
+  for (int i = 0; i < 4; ++i)
+    if (a.blocks_per_cu[i] != b.blocks_per_cu[i]) return false;
+  return true;
+}
+
+bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
+                            const bsm_pair *pairs, int npairs, hipStream_t s) {
   const int use_mask = ctx->use_mask;
   hipError_t e;
 
@@ -134,14 +158,16 @@ bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hip
   const size_t off_pairs = 0;
   const size_t off_order = align_up(off_pairs + npairs * sizeof(BatchPair), 256);
   const size_t off_start = align_up(off_order + npairs * sizeof(int), 256);
-  const size_t off_count = align_up(off_start + kBatchQueues * n1 * sizeof(int), 256);
-  const size_t table_bytes = align_up(off_count + kBatchQueues * sizeof(int), 256);
+  const size_t table_bytes = align_up(off_start + kBatchQueues * n1 * sizeof(int), 256);
   const size_t stage_bytes = table_bytes + sizeof(BatchWork);
 
   // The previous batch must be done with the staging buffer and the tables
   // before either is rewritten.
   if (b.launched && (e = hipEventSynchronize(b.done)) != hipSuccess)
     return device_fail(ctx, e, "waiting for the previous batch");
+  // A graph captured with other launch choices does not match the tile
+  // numbering below: capture again.
+  if (b.exec && !same_tuning(b.tune, dt.tune)) b.drop_graph();
   if (table_bytes > b.d_tables_cap) {
     if (b.d_tables) (void)hipFree(b.d_tables);
     b.d_tables = nullptr;
@@ -190,16 +216,15 @@ bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hip
     const bsm_pair &p = pairs[order[i]];
     horder[i] = order[i];
     int counts[kBatchQueues];
-    batch_tile_counts(p.width, p.height, use_mask, p.cost != nullptr, ctx->dt.tune.desc_tile_w,
+    batch_tile_counts(p.width, p.height, use_mask, p.cost != nullptr, dt.tune.desc_tile_w,
                       counts);
     for (int q = 0; q < kBatchQueues; ++q) hstart[q * n1 + i + 1] = hstart[q * n1 + i] + counts[q];
   }
-  std::memset(h + off_count, 0, kBatchQueues * sizeof(int));
   BatchWork *hw = reinterpret_cast<BatchWork *>(h + table_bytes);
   hw->pairs = reinterpret_cast<const BatchPair *>(b.d_tables + off_pairs);
   hw->order = reinterpret_cast<const int *>(b.d_tables + off_order);
   hw->start = reinterpret_cast<const int *>(b.d_tables + off_start);
-  hw->counters = reinterpret_cast<int *>(b.d_tables + off_count);
+  hw->counters = b.d_counters;  // zeroed by the graph's first node
   hw->npairs = npairs;
 
   if ((e = hipMemcpyAsync(b.d_tables, h, table_bytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -207,13 +232,13 @@ bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hip
           hipSuccess)
     return device_fail(ctx, e, "uploading the batch work list");
 
-  const BatchLaunch bl{b.d_work, hw->counters};
+  const BatchLaunch bl{b.d_work, b.d_counters};
   if (!b.exec) {
     // Capture the stage launches once; they read everything else from the
     // work list, so the graph serves every later batch of this context.
     if ((e = hipStreamBeginCapture(b.capture, hipStreamCaptureModeRelaxed)) != hipSuccess)
       return device_fail(ctx, e, "beginning batch graph capture");
-    hipError_t le = launch_batch(bl, ctx->dt, use_mask, b.capture);
+    hipError_t le = launch_batch(bl, dt, use_mask, b.capture);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b.capture, &g);
     if (le != hipSuccess || e != hipSuccess) {
@@ -225,6 +250,7 @@ bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hip
       b.drop_graph();
       return device_fail(ctx, e, "instantiating the batch graph");
     }
+    b.tune = dt.tune;
   }
   if ((e = hipGraphLaunch(b.exec, s)) != hipSuccess)
     return device_fail(ctx, e, "launching the batch graph");
@@ -234,23 +260,25 @@ bsm_status batch_persistent(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hip
   return BSM_OK;
 }
 
+}  // namespace
+
+bsm_status batch_run(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt, const bsm_pair *pairs,
+                     int npairs, hipStream_t s) {
+  if (!batch_supported(ctx->nw)) return batch_sequential(ctx, b, pairs, npairs, s);
+  return batch_persistent(ctx, b, dt, pairs, npairs, s);
+}
+
+namespace {
+
 bsm_status ensure_batch_state(bsm_ctx *ctx) {
   if (ctx->batch) return BSM_OK;
-  std::unique_ptr<BatchState> b(new BatchState);
-  hipError_t e;
-  if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipMalloc(&b->d_work, sizeof(BatchWork))) != hipSuccess)
-    return device_fail(ctx, e, "batch state");
-  ctx->batch = b.release();
-  return BSM_OK;
+  return batch_state_create(ctx, &ctx->batch);
 }
 
 bsm_status run_batch(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, hipStream_t s) {
   bsm_status st = ensure_batch_state(ctx);
   if (st != BSM_OK) return st;
-  if (!batch_supported(ctx->nw)) return batch_sequential(ctx, pairs, npairs, s);
-  return batch_persistent(ctx, pairs, npairs, s);
+  return batch_run(ctx, *ctx->batch, ctx->dt, pairs, npairs, s);
 }
 
 // RAII device switch for the entry points of this file.
@@ -295,6 +323,7 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
     return fail(BSM_EINVAL, "need npairs >= 1 and 1 <= reps <= 1000");
   OnDevice g(ctx->device);
   if (g.err != hipSuccess) return device_fail(ctx, g.err, "hipSetDevice");
+  if ((st = ensure_batch_state(ctx)) != BSM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e;
@@ -302,26 +331,26 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
     if (t0) (void)hipEventDestroy(t0);
     return device_fail(ctx, e, "autotune events");
   }
-  const Tuning start = ctx->dt.tune;
-  Tuning best_t = start;
+  Tuning best_t = ctx->dt.tune;
   double best_time = -1;
   // Candidates: describe tile width x cost window x cost / describe+mask
-  // persistent occupancy.
+  // persistent occupancy.  Each runs on a copy of the tables; the batch
+  // state recaptures its graph whenever the launch choices change.
   for (int tw : {16, 32})
     for (int dc : {32, 64})
       for (int cost_bpc : {0, 2})
         for (int mask_bpc : {0, 2}) {
-          Tuning t;
-          t.desc_tile_w = tw;
-          t.cost_dchunk = dc;
-          t.blocks_per_cu[1] = mask_bpc;
-          t.blocks_per_cu[3] = cost_bpc;
-          ctx->dt.tune = t;
-          batch_invalidate(ctx);
+          DeviceTables dt = ctx->dt;
+          dt.tune = Tuning();
+          dt.tune.desc_tile_w = tw;
+          dt.tune.cost_dchunk = dc;
+          dt.tune.blocks_per_cu[1] = mask_bpc;
+          dt.tune.blocks_per_cu[3] = cost_bpc;
           // one untimed run (captures the graph), then the timed runs
-          if ((st = run_batch(ctx, pairs, npairs, s)) != BSM_OK) break;
+          if ((st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s)) != BSM_OK) break;
           if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
-          for (int r = 0; r < reps && st == BSM_OK; ++r) st = run_batch(ctx, pairs, npairs, s);
+          for (int r = 0; r < reps && st == BSM_OK; ++r)
+            st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s);
           if (st != BSM_OK) break;
           if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
             break;
@@ -330,14 +359,16 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
           const double per = ms / reps;
           if (best_time < 0 || per < best_time) {
             best_time = per;
-            best_t = t;
+            best_t = dt.tune;
           }
         }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (st == BSM_OK && e != hipSuccess) st = device_fail(ctx, e, "autotune timing");
-  ctx->dt.tune = st == BSM_OK ? best_t : start;
-  batch_invalidate(ctx);
+  if (st == BSM_OK) {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->dt.tune = best_t;
+  }
   if (st != BSM_OK) return st;
   if (best) {
     best->desc_tile_w = best_t.desc_tile_w;

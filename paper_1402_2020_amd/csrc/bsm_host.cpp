@@ -540,8 +540,11 @@ bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *in) {
   t.desc_tile_w = in->desc_tile_w;
   t.cost_dchunk = in->cost_dchunk;
   for (int i = 0; i < 4; ++i) t.blocks_per_cu[i] = in->blocks_per_cu[i];
-  ctx->dt.tune = t;
-  batch_invalidate(ctx);  // a captured batch graph holds the old launch shapes
+  {
+    // batch states compare this with the choices their graphs hold
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->dt.tune = t;
+  }
   return BSM_OK;
 }
 

@@ -125,8 +125,11 @@ void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_
 // ---- batch (bsm_batch.cpp) --------------------------------------------------
 struct BatchState;
 void batch_state_free(BatchState *b);
-// Drops the captured batch graph (launch shapes changed).
-void batch_invalidate(bsm_ctx *ctx);
+bsm_status batch_state_create(bsm_ctx *ctx, BatchState **out);
+// Runs pairs (device pointers) as one batch with the given state, tables and
+// launch choices on stream s.
+bsm_status batch_run(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt, const bsm_pair *pairs,
+                     int npairs, hipStream_t s);
 
 // ---- device scratch with stream-ordered reuse ---------------------------
 // A growable device buffer.  Every use is recorded with an event; a use on
@@ -168,6 +171,7 @@ struct bsm_ctx {
   uint16_t *d_f = nullptr;
   int2 *d_right_offs = nullptr;
   bsm::DeviceTables dt{};
+  std::mutex tune_mu;  // guards dt.tune between its setters and the serving thread
   bsm::Scratch describe_scratch;  // packed colour plane of bsm_describe
   bsm::Scratch match_scratch;     // planes + descriptors of bsm_match
   bool dead = false;

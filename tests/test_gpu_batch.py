@@ -107,6 +107,30 @@ def test_batch_graph_reused_across_shapes_and_replays(torch_cuda, bsm, orc):
     ctx.close()
 
 
+def test_batch_graph_replays_as_the_pair_count_grows_and_shrinks(torch_cuda, bsm, orc):
+    # The replayed graph must reach the queue counters and the work tables of
+    # the current batch only: the tables are reallocated when a batch needs
+    # more pairs than any before it, and their layout moves with the count.
+    torch = torch_cuda
+    _say("case: batch graph replays with 1, 9, 3, 12 pairs, tuning changed between")
+    ctx, pat = _ctx(bsm, orc, 256, 15)
+    scenes = _scenes(12, 0.08, first=20)
+    want = [orc.match(s.left, s.right, pat, s.dmax)[0] for s in scenes]
+    tunings = [None, dict(desc_tile_w=32, cost_dchunk=32, blocks_per_cu=[0, 2, 0, 1]), None,
+               dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 0])]
+    for count, tune in zip((1, 9, 3, 12), tunings):
+        if tune is not None:
+            ctx.set_tuning(tune)
+        group = list(range(count))
+        items = [(_dev(torch, scenes[j].left), _dev(torch, scenes[j].right), scenes[j].dmax)
+                 for j in group]
+        outs = ctx.match_batch(items)
+        torch.cuda.synchronize()
+        for j, (disp, _) in zip(group, outs):
+            assert np.array_equal(disp.cpu().numpy(), want[j]), (count, j)
+    ctx.close()
+
+
 def test_batch_equals_single_pair_path_full_size(torch_cuda, bsm, orc):
     torch = torch_cuda
     _say("case: batch of 6 full-size uneven pairs == single-pair path")
