@@ -145,7 +145,7 @@ def bench_serve(args):
     gen_s = time.perf_counter() - t0
     pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
     ctx = _bsm.Context(n, S, sigma, pattern=pat, device=0)
-    ctx.serve_config(32 << 30, 1 << 16)
+    ctx.serve_config(32 << 30, 1 << 16, args.max_group)
     dev = torch.device("cuda:0")
     first = {}
 
@@ -239,8 +239,9 @@ def bench_serve(args):
         "data": "synthetic (seeded scene generator; Middlebury stand-in)",
         "config": {"workload": WORKLOADS[4], "rates_per_s": list(args.rates),
                    "duration_s": args.duration, "n_bits": n, "window": S,
-                   "admission_cap_bytes": 32 << 30},
+                   "admission_cap_bytes": 32 << 30, "max_group": args.max_group or 4},
         "rates": rates,
+        "serve_stats": ctx.serve_stats(),
         "results_identical": bool(same),
         "scene_generation_s": round(gen_s, 2),
         "roofline": None,
@@ -298,6 +299,8 @@ def main():
                     help="serving workload: seconds of arrivals per rate")
     ap.add_argument("--rates", type=int, nargs="+", default=[50, 200, 800],
                     help="serving workload: arrival rates, pairs/s")
+    ap.add_argument("--max-group", type=int, default=0,
+                    help="serving workload: most pairs per group (0: library default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (5 times), to scale "
                          "the HBM byte counters of a profiler run")

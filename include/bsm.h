@@ -211,8 +211,15 @@ bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t npairs,
                         double *best_ms);
 
 /* Serving: admission cap on the device working set of pairs in flight
- * (bytes; default 32 GiB) and the maximum number of queued requests. */
-bsm_status bsm_serve_config(bsm_ctx *ctx, size_t cap_bytes, int32_t max_queue);
+ * (bytes; default 32 GiB), the maximum number of queued requests (default
+ * 4096) and the most pairs one group may hold (0 = the default, 4).  A
+ * server starts on the first serving call; it admits waiting pairs in
+ * arrival order while their device bytes fit under the cap and runs each
+ * admitted group as one batch on one of three executor slots, so groups
+ * overlap on the device and pairs that arrive meanwhile join the next group
+ * (continuous batching). */
+bsm_status bsm_serve_config(bsm_ctx *ctx, size_t cap_bytes, int32_t max_queue,
+                            int32_t max_group);
 
 /* Serving: queues one pair given in HOST memory and returns a ticket.  The
  * library copies the images to the device when the pair is admitted and
@@ -230,6 +237,19 @@ bsm_status bsm_poll(bsm_ctx *ctx, uint64_t ticket, int32_t *state,
 
 /* Serving: blocks until every submitted pair is done or failed. */
 bsm_status bsm_drain(bsm_ctx *ctx);
+
+/* Serving counters since the server started. */
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t groups;              /* groups started on executor slots        */
+    uint64_t max_in_flight_bytes; /* largest admitted working set            */
+    int32_t max_group;            /* most pairs in one group                 */
+    int32_t max_slots_busy;       /* most groups running at once             */
+} bsm_serve_counters;
+
+/* Serving: copies the counters to *out (all zero before the first serving
+ * call).  BSM_EINVAL if ctx or out is NULL. */
+bsm_status bsm_serve_stats(bsm_ctx *ctx, bsm_serve_counters *out);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ INVALID_COST = 32767
 EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
            "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
            "bsm_match_batch", "bsm_get_tuning", "bsm_set_tuning", "bsm_autotune",
-           "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain")
+           "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain", "bsm_serve_stats")
 
 
 class BsmError(RuntimeError):
@@ -44,6 +44,15 @@ class Pair(C.Structure):
 class Times(C.Structure):
     _fields_ = [("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_start", C.c_double),
                 ("t_end", C.c_double)]
+
+
+class ServeCounters(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("groups", C.c_uint64), ("max_in_flight_bytes", C.c_uint64),
+                ("max_group", C.c_int32), ("max_slots_busy", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Tuning(C.Structure):
@@ -95,7 +104,8 @@ def load():
         "bsm_set_tuning": ([vp, C.POINTER(Tuning)], st),
         "bsm_autotune": ([vp, C.POINTER(Pair), i32, i32, vp, C.POINTER(Tuning),
                           C.POINTER(C.c_double)], st),
-        "bsm_serve_config": ([vp, sz, i32], st),
+        "bsm_serve_config": ([vp, sz, i32, i32], st),
+        "bsm_serve_stats": ([vp, C.POINTER(ServeCounters)], st),
         "bsm_submit": ([vp, C.POINTER(Pair), C.POINTER(u64)], st),
         "bsm_poll": ([vp, u64, C.POINTER(i32), C.POINTER(Times)], st),
         "bsm_drain": ([vp], st),
@@ -198,8 +208,14 @@ def bsm_autotune(ctx, pairs, reps, stream):
     return st, best, ms.value
 
 
-def bsm_serve_config(ctx, cap_bytes, max_queue):
-    return load().bsm_serve_config(ctx, cap_bytes, max_queue)
+def bsm_serve_config(ctx, cap_bytes, max_queue, max_group=0):
+    return load().bsm_serve_config(ctx, cap_bytes, max_queue, max_group)
+
+
+def bsm_serve_stats(ctx):
+    out = ServeCounters()
+    st = load().bsm_serve_stats(ctx, C.byref(out))
+    return st, out
 
 
 def bsm_submit(ctx, pair):
@@ -357,8 +373,13 @@ class Context:
 
     # ---- serving (host buffers) -------------------------------------------
 
-    def serve_config(self, cap_bytes, max_queue):
-        _check(bsm_serve_config(self.h, cap_bytes, max_queue), "bsm_serve_config")
+    def serve_config(self, cap_bytes, max_queue, max_group=0):
+        _check(bsm_serve_config(self.h, cap_bytes, max_queue, max_group), "bsm_serve_config")
+
+    def serve_stats(self):
+        st, out = bsm_serve_stats(self.h)
+        _check(st, "bsm_serve_stats")
+        return out.as_dict()
 
     def submit(self, left, right, dmax, want_cost=False):
         """Queues one pair of uint8 host arrays [H][W][3] (numpy); returns a

@@ -19,8 +19,8 @@ double Server::now() {
   return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
 }
 
-Server::Server(std::unique_ptr<Executor> exec, size_t cap_bytes, int max_queue)
-    : exec_(std::move(exec)), cap_(cap_bytes), max_queue_(max_queue) {
+Server::Server(std::unique_ptr<Executor> exec, size_t cap_bytes, int max_queue, int max_group)
+    : exec_(std::move(exec)), cap_(cap_bytes), max_queue_(max_queue), max_group_(max_group) {
   running_.resize(exec_->slots());
   thread_ = std::thread([this] { loop(); });
 }
@@ -34,11 +34,12 @@ Server::~Server() {
   if (thread_.joinable()) thread_.join();
 }
 
-void Server::configure(size_t cap_bytes, int max_queue) {
+void Server::configure(size_t cap_bytes, int max_queue, int max_group) {
   {
     std::lock_guard<std::mutex> lk(mu_);
     cap_ = cap_bytes;
     max_queue_ = max_queue;
+    max_group_ = max_group;
   }
   wake_.notify_all();
 }
@@ -139,7 +140,8 @@ void Server::loop() {
       }
       if (free_slot >= 0) {
         const double t = now();
-        while (!waiting_.empty() && in_flight_ + waiting_.front()->bytes <= cap_) {
+        while (!waiting_.empty() && (int)group.size() < max_group_ &&
+               in_flight_ + waiting_.front()->bytes <= cap_) {
           Request *r = waiting_.front();
           waiting_.pop_front();
           r->times.t_admit = t;

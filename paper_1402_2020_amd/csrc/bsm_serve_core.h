@@ -5,10 +5,11 @@
 // executor in CPU tests.
 //
 // Requests wait in arrival order.  Whenever an executor slot is free, the
-// server admits the longest prefix of the waiting queue whose device
-// footprints fit under the cap next to everything in flight, hands that
-// group to the slot and goes on; groups on different slots run at the same
-// time.  A request is in one of: waiting, running, done or failed.
+// server admits the longest prefix of the waiting queue (at most max_group
+// requests) whose device footprints fit under the cap next to everything in
+// flight, hands that group to the slot and goes on; groups on different
+// slots run at the same time.  A request is in one of: waiting, running,
+// done or failed.
 #pragma once
 
 #include <chrono>
@@ -50,10 +51,10 @@ class Executor {
 class Server {
  public:
   using Clock = std::chrono::steady_clock;
-  Server(std::unique_ptr<Executor> exec, size_t cap_bytes, int max_queue);
+  Server(std::unique_ptr<Executor> exec, size_t cap_bytes, int max_queue, int max_group);
   ~Server();  // stops the thread after the work in flight ends
 
-  void configure(size_t cap_bytes, int max_queue);
+  void configure(size_t cap_bytes, int max_queue, int max_group);
   // BSM_ETOOBIG if bytes > cap; BSM_EAGAIN if the waiting queue is full.
   bsm_status submit(const bsm_pair &pair, size_t bytes, uint64_t *ticket);
   // BSM_ENOTFOUND for unknown (or already reported finished) tickets.
@@ -81,7 +82,7 @@ class Server {
   std::map<uint64_t, std::unique_ptr<Request>> all_;
   std::vector<std::vector<Request *>> running_;  // per slot
   size_t cap_ = 0, in_flight_ = 0;
-  int max_queue_ = 0;
+  int max_queue_ = 0, max_group_ = 1;
   uint64_t next_ticket_ = 1;
   uint64_t unfinished_ = 0;  // waiting + running
   bool stop_ = false;

@@ -8,6 +8,7 @@
 // different slots overlap on the device.  When the slot's event completes,
 // the results are copied from pinned memory into the caller's buffers.
 #include <cstring>
+#include <functional>
 #include <map>
 
 #include "bsm_internal.h"
@@ -51,6 +52,112 @@ class PinnedPool {
   std::map<void *, size_t> size_;
 };
 
+// A few host threads that run copy tasks beside the calling thread.  Host
+// copies between the caller's pageable buffers and pinned staging are the
+// serving path's host-side cost; spreading them over threads keeps the
+// server thread free to retire and admit.
+class CopyPool {
+ public:
+  explicit CopyPool(int workers) {
+    for (int i = 0; i < workers; ++i) threads_.emplace_back([this] { work(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto &t : threads_) t.join();
+  }
+  // Runs fn(i) for i in [0, n) on the workers and the calling thread and
+  // returns when all calls have returned.  One run at a time.
+  void run(int n, const std::function<void(int)> &fn) {
+    if (n <= 0) return;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_ = 0;
+      pending_ = n;
+      ++gen_;
+    }
+    cv_.notify_all();
+    drain_tasks();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [this] { return pending_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void drain_tasks() {
+    for (;;) {
+      int i;
+      const std::function<void(int)> *fn;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!fn_ || next_ >= n_) return;
+        i = next_++;
+        fn = fn_;
+      }
+      (*fn)(i);
+      bool last;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        last = --pending_ == 0;
+      }
+      if (last) done_.notify_all();
+    }
+  }
+  void work() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      drain_tasks();
+    }
+  }
+
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)> *fn_ = nullptr;
+  int n_ = 0, next_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+  std::vector<std::thread> threads_;
+};
+
+// One strided block copy (rows of `bytes` bytes).
+struct CopyTask {
+  char *dst;
+  const char *src;
+  size_t dst_pitch, src_pitch, bytes;
+  int rows;
+};
+
+// Appends the copy of `rows` rows as tasks of about 512 KiB each.
+void add_rows(std::vector<CopyTask> &tasks, char *dst, size_t dst_pitch, const char *src,
+              size_t src_pitch, size_t bytes, int rows) {
+  const int per = (int)std::max<size_t>(1, (512 << 10) / std::max<size_t>(bytes, 1));
+  for (int r = 0; r < rows; r += per)
+    tasks.push_back(CopyTask{dst + r * dst_pitch, src + r * src_pitch, dst_pitch, src_pitch, bytes,
+                             std::min(per, rows - r)});
+}
+
+void run_copies(CopyPool &pool, const std::vector<CopyTask> &tasks) {
+  pool.run((int)tasks.size(), [&](int i) {
+    const CopyTask &t = tasks[i];
+    if (t.dst_pitch == t.bytes && t.src_pitch == t.bytes) {
+      std::memcpy(t.dst, t.src, t.bytes * t.rows);
+      return;
+    }
+    for (int r = 0; r < t.rows; ++r) std::memcpy(t.dst + r * t.dst_pitch, t.src + r * t.src_pitch, t.bytes);
+  });
+}
+
 // Layout of one request's device buffer and pinned staging buffer.
 struct Layout {
   size_t img, disp, cost, total, in_bytes;
@@ -63,6 +170,8 @@ struct Layout {
     total = 2 * img + disp + cost;
   }
 };
+
+constexpr int kCopyThreads = 3;  // plus the server thread
 
 class HipExecutor : public Executor {
  public:
@@ -82,8 +191,9 @@ class HipExecutor : public Executor {
     if (hipSetDevice(ctx_->device) != hipSuccess) return false;
     if (!s.stream && !init(s)) return false;
     s.pinned.assign(group.size(), nullptr);
-    s.device.assign(group.size(), nullptr);
+    std::vector<char *> device(group.size(), nullptr);
     std::vector<bsm_pair> pairs(group.size());
+    std::vector<CopyTask> tasks;
     bool ok = true;
     for (size_t i = 0; i < group.size() && ok; ++i) {
       const bsm_pair &p = group[i]->pair;
@@ -96,14 +206,12 @@ class HipExecutor : public Executor {
         break;
       }
       s.pinned[i] = h;
-      s.device[i] = d;
-      // compact the caller's rows into pinned memory, then copy to the device
+      device[i] = d;
+      // the caller's rows, compacted into pinned memory
       const size_t row = (size_t)p.width * 3;
-      for (int v = 0; v < p.height; ++v) {
-        std::memcpy(h + v * row, p.left + (size_t)v * p.stride, row);
-        std::memcpy(h + L.img + v * row, p.right + (size_t)v * p.stride, row);
-      }
-      ok = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s.stream) == hipSuccess;
+      add_rows(tasks, h, row, reinterpret_cast<const char *>(p.left), p.stride, row, p.height);
+      add_rows(tasks, h + L.img, row, reinterpret_cast<const char *>(p.right), p.stride, row,
+               p.height);
       pairs[i] = bsm_pair{reinterpret_cast<const uint8_t *>(d),
                           reinterpret_cast<const uint8_t *>(d + L.img),
                           p.width,
@@ -114,6 +222,12 @@ class HipExecutor : public Executor {
                           p.cost ? reinterpret_cast<int16_t *>(d + L.in_bytes + L.disp) : nullptr};
     }
     if (ok) {
+      run_copies(copies_, tasks);
+      for (size_t i = 0; i < group.size() && ok; ++i)
+        ok = hipMemcpyAsync(device[i], s.pinned[i], Layout(group[i]->pair).in_bytes,
+                            hipMemcpyHostToDevice, s.stream) == hipSuccess;
+    }
+    if (ok) {
       DeviceTables dt;
       {
         std::lock_guard<std::mutex> lk(ctx_->tune_mu);
@@ -122,18 +236,20 @@ class HipExecutor : public Executor {
       ok = batch_run(ctx_, *s.batch, dt, pairs.data(), (int)pairs.size(), s.stream) == BSM_OK;
     }
     for (size_t i = 0; i < group.size(); ++i) {
-      if (!s.device[i]) continue;
+      if (!device[i]) continue;
       if (ok) {
         const Layout L(group[i]->pair);
-        ok = hipMemcpyAsync(static_cast<char *>(s.pinned[i]) + L.in_bytes,
-                            static_cast<char *>(s.device[i]) + L.in_bytes, L.total - L.in_bytes,
-                            hipMemcpyDeviceToHost, s.stream) == hipSuccess;
+        ok = hipMemcpyAsync(static_cast<char *>(s.pinned[i]) + L.in_bytes, device[i] + L.in_bytes,
+                            L.total - L.in_bytes, hipMemcpyDeviceToHost, s.stream) == hipSuccess;
       }
-      (void)hipFreeAsync(s.device[i], s.stream);
-      s.device[i] = nullptr;
+      (void)hipFreeAsync(device[i], s.stream);
     }
     if (ok) ok = hipEventRecord(s.event, s.stream) == hipSuccess;
-    if (!ok) release(s);
+    if (!ok) {
+      // nothing may still write the pinned buffers when they go back
+      (void)hipStreamSynchronize(s.stream);
+      release(s);
+    }
     return ok;
   }
 
@@ -147,14 +263,18 @@ class HipExecutor : public Executor {
 
   bool finish(int slot, const std::vector<Request *> &group) override {
     Slot &s = slots_[slot];
+    std::vector<CopyTask> tasks;
     for (size_t i = 0; i < group.size(); ++i) {
       const bsm_pair &p = group[i]->pair;
       const Layout L(p);
       const char *h = static_cast<const char *>(s.pinned[i]);
-      std::memcpy(p.disp, h + L.in_bytes, (size_t)p.width * p.height * 4);
+      const size_t row = (size_t)p.width * 4;
+      add_rows(tasks, reinterpret_cast<char *>(p.disp), row, h + L.in_bytes, row, row, p.height);
       if (p.cost)
-        std::memcpy(p.cost, h + L.in_bytes + L.disp, (size_t)p.width * p.height * p.dmax * 2);
+        add_rows(tasks, reinterpret_cast<char *>(p.cost), row / 2, h + L.in_bytes + L.disp, row / 2,
+                 row / 2, p.height * p.dmax);
     }
+    run_copies(copies_, tasks);
     release(s);
     return true;
   }
@@ -164,7 +284,7 @@ class HipExecutor : public Executor {
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
     BatchState *batch = nullptr;
-    std::vector<void *> pinned, device;
+    std::vector<void *> pinned;  // staging of the group in flight
   };
 
   bool init(Slot &s) {
@@ -191,10 +311,12 @@ class HipExecutor : public Executor {
   bsm_ctx *ctx_;
   std::vector<Slot> slots_;
   PinnedPool pool_;
+  CopyPool copies_{kCopyThreads};
 };
 
 constexpr size_t kDefaultCap = size_t(32) << 30;  // 32 GiB
 constexpr int kDefaultQueue = 4096;
+constexpr int kDefaultGroup = 4;
 constexpr int kSlots = 3;
 
 // Device bytes one request holds while admitted: its buffers (images,
@@ -210,7 +332,7 @@ Server *server_of(bsm_ctx *ctx) {
   if (!ctx->server)
     ctx->server =
         new Server(std::unique_ptr<Executor>(new HipExecutor(ctx, kSlots)), kDefaultCap,
-                   kDefaultQueue);
+                   kDefaultQueue, kDefaultGroup);
   return ctx->server;
 }
 
@@ -224,13 +346,35 @@ using namespace bsm;
 
 extern "C" {
 
-bsm_status bsm_serve_config(bsm_ctx *ctx, size_t cap_bytes, int32_t max_queue) {
+bsm_status bsm_serve_config(bsm_ctx *ctx, size_t cap_bytes, int32_t max_queue,
+                            int32_t max_group) {
   clear_error();
   bsm_status st;
   if ((st = check_alive(ctx)) != BSM_OK) return st;
-  if (cap_bytes == 0 || max_queue < 1)
-    return fail(BSM_EINVAL, "cap_bytes must be > 0 and max_queue >= 1");
-  server_of(ctx)->configure(cap_bytes, max_queue);
+  if (cap_bytes == 0 || max_queue < 1 || max_group < 0)
+    return fail(BSM_EINVAL, "need cap_bytes > 0, max_queue >= 1 and max_group >= 0");
+  server_of(ctx)->configure(cap_bytes, max_queue, max_group ? max_group : kDefaultGroup);
+  return BSM_OK;
+}
+
+bsm_status bsm_serve_stats(bsm_ctx *ctx, bsm_serve_counters *out) {
+  clear_error();
+  if (!ctx || !out) return fail(BSM_EINVAL, "context and out must not be NULL");
+  Server *s;
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    s = ctx->server;
+  }
+  *out = bsm_serve_counters{};
+  if (!s) return BSM_OK;
+  const Server::Stats st = s->stats();
+  out->submitted = st.submitted;
+  out->completed = st.completed;
+  out->failed = st.failed;
+  out->groups = st.groups;
+  out->max_in_flight_bytes = st.max_in_flight_bytes;
+  out->max_group = st.max_group;
+  out->max_slots_busy = st.max_slots_busy;
   return BSM_OK;
 }
 

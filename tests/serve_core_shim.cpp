@@ -56,10 +56,10 @@ struct Shim {
 
 extern "C" {
 
-void *shim_create(size_t cap, int max_queue, int slots, double work_ms) {
+void *shim_create(size_t cap, int max_queue, int slots, double work_ms, int max_group) {
   auto *e = new FakeExecutor(slots, work_ms);
   auto *s = new Shim{e, nullptr};
-  s->server = new Server(std::unique_ptr<Executor>(e), cap, max_queue);
+  s->server = new Server(std::unique_ptr<Executor>(e), cap, max_queue, max_group);
   return s;
 }
 
@@ -69,8 +69,8 @@ void shim_destroy(void *h) {
   delete s;
 }
 
-void shim_configure(void *h, size_t cap, int max_queue) {
-  static_cast<Shim *>(h)->server->configure(cap, max_queue);
+void shim_configure(void *h, size_t cap, int max_queue, int max_group) {
+  static_cast<Shim *>(h)->server->configure(cap, max_queue, max_group);
 }
 
 int shim_submit(void *h, const uint8_t *left, const uint8_t *right, int W, int H, int dmax,
@@ -121,7 +121,7 @@ double shim_now() { return Server::now(); }
 #include <cstdio>
 #include <vector>
 int main() {
-  void *h = shim_create(1000, 64, 3, 0.2);
+  void *h = shim_create(1000, 64, 3, 0.2, 4);
   std::atomic<int> bad{0};
   std::vector<std::thread> clients;
   for (int c = 0; c < 4; ++c)

@@ -43,39 +43,30 @@ def test_library_exports_every_declared_symbol(lib):
     assert set(_declared_functions()) <= exported
 
 
+STRUCTS = (("bsm_params", "Params"), ("bsm_pair", "Pair"), ("bsm_times", "Times"),
+           ("bsm_tuning", "Tuning"), ("bsm_serve_counters", "ServeCounters"))
+
+
 def test_struct_layouts_match_header(tmp_path):
+    # sizes and every field offset, from the C compiler vs the ctypes classes
+    lines = []
+    for T, cname in STRUCTS:
+        lines.append(f'  printf("{T} %zu\\n", sizeof({T}));')
+        for fname, _ in getattr(_bsm, cname)._fields_:
+            lines.append(f'  printf("{T}.{fname} %zu\\n", offsetof({T}, {fname}));')
     src = tmp_path / "layout.c"
-    src.write_text(r'''
-#include <stddef.h>
-#include <stdio.h>
-#include "bsm.h"
-#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
-int main(void) {
-  printf("bsm_params %zu\n", sizeof(bsm_params));
-  F(bsm_params, n_bits); F(bsm_params, window); F(bsm_params, sigma); F(bsm_params, seed);
-  F(bsm_params, pattern); F(bsm_params, mask_rank); F(bsm_params, use_mask);
-  printf("bsm_pair %zu\n", sizeof(bsm_pair));
-  F(bsm_pair, left); F(bsm_pair, right); F(bsm_pair, width); F(bsm_pair, height);
-  F(bsm_pair, stride); F(bsm_pair, dmax); F(bsm_pair, disp); F(bsm_pair, cost);
-  printf("bsm_times %zu\n", sizeof(bsm_times));
-  F(bsm_times, t_arrive); F(bsm_times, t_end);
-  return 0;
-}
-''')
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"bsm.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\n  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
                    check=True)
     got = dict(ln.rsplit(" ", 1) for ln in subprocess.run([str(exe)], capture_output=True,
                                                            text=True).stdout.splitlines())
-    want = {"bsm_params": C.sizeof(_bsm.Params), "bsm_pair": C.sizeof(_bsm.Pair),
-            "bsm_times": C.sizeof(_bsm.Times)}
-    for T, cls in (("bsm_params", _bsm.Params), ("bsm_pair", _bsm.Pair), ("bsm_times", _bsm.Times)):
+    for T, cname in STRUCTS:
+        cls = getattr(_bsm, cname)
+        assert int(got[T]) == C.sizeof(cls), T
         for fname, _ in cls._fields_:
-            key = f"{T}.{fname}"
-            if key in got:
-                assert int(got[key]) == getattr(cls, fname).offset, key
-    for k, v in want.items():
-        assert int(got[k]) == v, k
+            assert int(got[f"{T}.{fname}"]) == getattr(cls, fname).offset, (T, fname)
 
 
 @pytest.mark.parametrize("seed,n,S,sigma", [(0, 64, 3, 0.8), (14022020, 256, 15, 4 * 15 / 26),

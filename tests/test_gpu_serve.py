@@ -92,6 +92,12 @@ def test_serve_groups_of_growing_size_on_one_slot(torch_cuda, bsm, orc):
             state, _, (disp, _) = ctx.poll(t)
             assert state == 1
             assert np.array_equal(disp, want[j]), (burst, j)
+    st = ctx.serve_stats()
+    _say(f"serve stats: {st}")
+    assert st["completed"] == 18 and st["failed"] == 0
+    # the burst of 12 arrived while earlier work ran: later pairs were
+    # grouped, and groups ran on more than one slot at once
+    assert st["max_group"] > 1 and st["max_slots_busy"] > 1
     ctx.close()
 
 
@@ -176,6 +182,9 @@ def test_serve_invalid_arguments(torch_cuda, bsm, orc):
     assert e.value.status == bsm.EINVAL
     with pytest.raises(bsm.BsmError) as e:
         ctx.serve_config(0, 1)
+    assert e.value.status == bsm.EINVAL
+    with pytest.raises(bsm.BsmError) as e:
+        ctx.serve_config(1 << 30, 1, -1)
     assert e.value.status == bsm.EINVAL
     with pytest.raises(bsm.BsmError) as e:
         ctx.poll(99)

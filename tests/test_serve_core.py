@@ -23,10 +23,10 @@ def shim(tmp_path_factory):
                     str(out)], check=True)
     lib = C.CDLL(str(out))
     vp, sz, u64p = C.c_void_p, C.c_size_t, C.POINTER(C.c_uint64)
-    lib.shim_create.argtypes = [sz, C.c_int, C.c_int, C.c_double]
+    lib.shim_create.argtypes = [sz, C.c_int, C.c_int, C.c_double, C.c_int]
     lib.shim_create.restype = vp
     lib.shim_destroy.argtypes = [vp]
-    lib.shim_configure.argtypes = [vp, sz, C.c_int]
+    lib.shim_configure.argtypes = [vp, sz, C.c_int, C.c_int]
     lib.shim_submit.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, sz, u64p]
     lib.shim_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.shim_drain.argtypes = [vp]
@@ -37,9 +37,9 @@ def shim(tmp_path_factory):
 
 
 class Client:
-    def __init__(self, lib, cap, queue, slots, work_ms):
+    def __init__(self, lib, cap, queue, slots, work_ms, max_group=1 << 20):
         self.lib = lib
-        self.h = lib.shim_create(cap, queue, slots, work_ms)
+        self.h = lib.shim_create(cap, queue, slots, work_ms, max_group)
         self.keep = {}
 
     def submit(self, bytes_, W=4, H=3, dmax=2, seed=0):
@@ -119,6 +119,16 @@ def test_continuous_batching_overlaps_slots(shim):
     c.close()
 
 
+def test_group_size_limit(shim):
+    c = Client(shim, 10_000, 1000, 2, 5.0, max_group=4)
+    tickets = [c.submit(100, seed=i)[1] for i in range(40)]
+    shim.shim_drain(c.h)
+    assert all(c.poll(t)[1] == 1 for t in tickets)
+    st = c.stats()
+    assert st["completed"] == 40 and 1 < st["max_group"] <= 4
+    c.close()
+
+
 def test_cap_limits_bytes_in_flight(shim):
     c = Client(shim, 1000, 1000, 3, 1.0)
     for i in range(40):
@@ -159,7 +169,7 @@ def test_lowering_cap_fails_waiting_requests_that_no_longer_fit(shim):
     while c.poll(t1)[2][1] == 0.0:  # until t1 is admitted
         assert time.time() - t0 < 5
         time.sleep(0.0005)
-    shim.shim_configure(c.h, 500, 100)
+    shim.shim_configure(c.h, 500, 100, 1 << 20)
     assert c.wait(t1)[1] == 1       # already admitted
     assert c.wait(t2)[1] == -1      # can never fit any more
     c.close()
