@@ -195,16 +195,27 @@ void build_color_tables(ColorTables *t) {
 // fewest cycles summed over all words and both samples.
 // ---------------------------------------------------------------------------
 int choose_left_pitch(const int8_t *pattern, int n, int cols) {
+  // The describe+mask kernel's gathers: for slot j, lane l reads the
+  // samples of pair NW l + j (NW >= 8) or 64 j + l (NW <= 4); pairs past n
+  // read the centre.  Each half-wave's 32 lanes are served together, one
+  // cycle per lane that shares a bank with earlier ones.
+  int NW = 1;
+  while (NW < n / 64) NW *= 2;
   int best_pitch = cols, best_cycles = -1;
   for (int pitch = cols; pitch < cols + 32; ++pitch) {
     int cycles = 0;
-    for (int word = 0; word < n / 64; ++word)
+    for (int j = 0; j < NW; ++j)
       for (int sample = 0; sample < 2; ++sample)
         for (int half = 0; half < 2; ++half) {
           int load[32] = {0}, worst = 0;
-          for (int l = 0; l < 32; ++l) {
-            const int8_t *o = pattern + 4 * (64 * word + 32 * half + l) + 2 * sample;
-            const int bank = ((o[1] * pitch + o[0]) % 32 + 32) % 32;
+          for (int l = 32 * half; l < 32 * half + 32; ++l) {
+            const int i = NW >= 8 ? NW * l + j : 64 * j + l;
+            int dx = 0, dy = 0;
+            if (i < n) {
+              dx = pattern[4 * i + 2 * sample];
+              dy = pattern[4 * i + 2 * sample + 1];
+            }
+            const int bank = ((dy * pitch + dx) % 32 + 32) % 32;
             worst = std::max(worst, ++load[bank]);
           }
           cycles += worst;

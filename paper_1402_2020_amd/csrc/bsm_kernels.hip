@@ -81,13 +81,31 @@ __global__ __launch_bounds__(kColorThreads) void k_color(const uint8_t *__restri
 // Descriptor + mask (reference view).  A block stages a TH x TW tile of
 // packed pixels plus a halo of `radius` in LDS (coordinates clamped to the
 // image, which is exactly the border rule).  Each wave walks its pixels one
-// at a time with the 64 lanes spread over point pairs: lane l of word j
-// evaluates pair 64 j + l, so the wave-wide ballot of the binary test IS
-// word j of B(x) (bit l = pair 64 j + l + 1).  Each lane keeps its pair
-// weights in registers; T, the k-th smallest weight, is found by bisection,
-// each probe counting ballot(w <= t) words with a scalar popcount.
+// at a time with the 64 lanes spread over the point pairs and every pair
+// weight kept in registers.  T, the k-th smallest weight, is the smallest t
+// with #{w <= t} >= k; a probe counts ballot(w <= t) words with scalar
+// popcounts, and the search starts from the wave's previous pixel's T
+// (neighbouring pixels have close thresholds): it gallops away from it in
+// doubling steps until T is bracketed, then bisects.
+//
+// Pair-to-lane maps (NW = nw rounded up to a power of two, padded pairs
+// compare the centre with itself: weight 0, and each shifts the rank of T
+// by one):
+//   NW >= 8  lane l owns pairs NW l .. NW l + NW - 1, so its binary tests
+//            are NW consecutive bits of the descriptor (and of the mask):
+//            the lane shifts them into a register and stores its NW / 8
+//            bytes itself; the wave's stores cover the pixel's words.
+//   NW <= 4  lane l of word j owns pair 64 j + l, so the ballot of the
+//            wave's tests IS word j, moved into lane j with v_writelane.
 // ===========================================================================
 constexpr int kDescTH = 8, kDescThreads = 256;
+constexpr int kGallopStep = 8;  // first step of the threshold search
+
+// Pair index of slot j of lane `lane` (0-based).
+template <int NW>
+__device__ __forceinline__ int pair_of(int lane, int j) {
+  return NW >= 8 ? NW * lane + j : 64 * j + lane;
+}
 
 // v_writelane_b32 through the LLVM intrinsic (this clang has no builtin for
 // it), so that the compiler's hazard handling sees it: an SGPR written by a
@@ -112,58 +130,164 @@ __device__ __forceinline__ void for_words(F &&f) {
   }
 }
 
+// #{w <= t} >= k over the wave's weights (t wave-uniform).
+template <int NW>
+__device__ __forceinline__ bool rank_reached(const uint32_t *w, int t, int k) {
+  int count = 0;
+#pragma unroll
+  for (int j = 0; j < NW; ++j) count += __popcll(__ballot(w[j] <= (uint32_t)t));
+  return count >= k;
+}
+
+// The k-th smallest weight (Eq. 6: T), searched from `guess`.  Weights lie
+// in [0, 765] (three byte differences), so t = 765 always reaches rank k
+// and t = -1 never does.
+template <int NW>
+__device__ __forceinline__ int kth_smallest(const uint32_t *w, int k, int guess) {
+  constexpr int kTop = 765;
+  int lo, hi;  // rank not reached at lo, reached at hi
+  if (rank_reached<NW>(w, guess, k)) {
+    hi = guess;
+    for (int step = kGallopStep;; step <<= 1) {
+      const int t = hi - step;
+      if (t < 0) {
+        lo = -1;
+        break;
+      }
+      if (!rank_reached<NW>(w, t, k)) {
+        lo = t;
+        break;
+      }
+      hi = t;
+    }
+  } else {
+    lo = guess;
+    for (int step = kGallopStep;; step <<= 1) {
+      const int t = lo + step;
+      if (t >= kTop) {
+        hi = kTop;
+        break;
+      }
+      if (rank_reached<NW>(w, t, k)) {
+        hi = t;
+        break;
+      }
+      lo = t;
+    }
+  }
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rank_reached<NW>(w, mid, k))
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+// Pair weights of Eq. 5: max of the CIELAB SADs of the two samples to the
+// centre.  Packed pixels hold L8, a8, b8 in bytes 0-2 and I in byte 3.
+// v_msad_u8 leaves out the bytes where its second operand is 0, so with the
+// centre's byte 3 cleared it sums exactly the three colour differences, as
+// long as none of the centre's colour bytes is 0; otherwise the samples'
+// byte 3 is masked off first.  `centre` is wave-uniform.
+template <int NW>
+__device__ __forceinline__ void pair_weights(const uint32_t *a, const uint32_t *b,
+                                             uint32_t centre, uint32_t *w) {
+  const uint32_t c = centre & 0xffffffu;
+  const bool colour_nonzero = (c & 0xffu) && (c & 0xff00u) && (c & 0xff0000u);
+  if (colour_nonzero) {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t sp = __builtin_amdgcn_msad_u8(a[j], c, 0u);
+      const uint32_t sq = __builtin_amdgcn_msad_u8(b[j], c, 0u);
+      w[j] = sp > sq ? sp : sq;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t sp = __builtin_amdgcn_sad_u8(a[j] & 0xffffffu, c, 0u);
+      const uint32_t sq = __builtin_amdgcn_sad_u8(b[j] & 0xffffffu, c, 0u);
+      w[j] = sp > sq ? sp : sq;
+    }
+  }
+}
+
+// Stores a lane's NW consecutive bits (NW >= 8) at byte NW / 8 * lane of
+// the pixel's words.
+template <int NW>
+__device__ __forceinline__ void store_lane_bits(uint64_t *out, int lane, const uint32_t *bits) {
+  if constexpr (NW == 8) {
+    reinterpret_cast<uint8_t *>(out)[lane] = static_cast<uint8_t>(bits[0]);
+  } else if constexpr (NW == 16) {
+    reinterpret_cast<uint16_t *>(out)[lane] = static_cast<uint16_t>(bits[0]);
+  } else if constexpr (NW == 32) {
+    reinterpret_cast<uint32_t *>(out)[lane] = bits[0];
+  } else {
+    static_assert(NW == 64, "lane-major descriptors need NW in {8, 16, 32, 64}");
+    reinterpret_cast<uint2 *>(out)[lane] = make_uint2(bits[0], bits[1]);
+  }
+}
+
 // One pixel of the descriptor and mask.  ap/aq: LDS byte addresses of this
 // lane's samples for the group's first pixel; `shift` (bytes, compile-time
 // after unrolling) moves them to this pixel through the instruction's
-// immediate offset.  out: this pixel's words in desc / mask.
+// immediate offset.  out: this pixel's words in desc / mask.  Returns T.
 template <int NW>
-__device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, const int *aq,
-                                               int centre_addr, int shift, int lane, int nw,
-                                               int k_eff, uint64_t *out_desc,
-                                               uint64_t *out_mask) {
+__device__ __forceinline__ int describe_pixel(const char *lds, const int *ap, const int *aq,
+                                              int centre_addr, int shift, int lane, int n,
+                                              int k_eff, int guess, uint64_t *out_desc,
+                                              uint64_t *out_mask) {
   uint32_t a[NW], b[NW];
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
     a[j] = *reinterpret_cast<const uint32_t *>(lds + ap[j] + shift);
     b[j] = *reinterpret_cast<const uint32_t *>(lds + aq[j] + shift);
   }
-  uint32_t d_lo = 0, d_hi = 0;
-  for_words<NW>([&](auto J) {  // tau of Eq. 3
-    put_word<J.value>(__ballot((a[J.value] >> 24) > (b[J.value] >> 24)), d_lo, d_hi);
-  });
-  const uint32_t centre = *reinterpret_cast<const uint32_t *>(lds + centre_addr) & 0xffffffu;
-  uint32_t w[NW];
-  uint32_t wmax = 0;
+  const uint32_t centre = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(
+      *reinterpret_cast<const int *>(lds + centre_addr)));
+  if constexpr (NW >= 8) {
+    // tau of Eq. 3 and delta of Eq. 6, slot j -> bit j of the lane's chunk.
+    // Each test is the sign of a difference, shifted in by v_alignbit:
+    // I(q) - I(p) < 0 exactly when tau = 1, w - T - 1 < 0 exactly when
+    // delta = 1 (both differences are small, so nothing wraps).  The
+    // descriptor bits are taken first so that the samples are dead during
+    // the threshold search.
+    constexpr int kRegs = (NW + 31) / 32;
+    uint32_t d[kRegs], m[kRegs];
 #pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const uint32_t sp = __builtin_amdgcn_sad_u8(a[j] & 0xffffffu, centre, 0u);
-    const uint32_t sq = __builtin_amdgcn_sad_u8(b[j] & 0xffffffu, centre, 0u);
-    w[j] = sp > sq ? sp : sq;  // Eq. 5
-    wmax = wmax > w[j] ? wmax : w[j];
-  }
-  // T is the smallest t with #{w <= t} >= k (the k-th smallest weight).  It
-  // lies in [0, max w]; narrow [0, 1023] to the smallest power-of-two range
-  // holding max w, then bisect.
-  int hi = 1023;
-  while (hi > 0 && __ballot(wmax > (uint32_t)(hi >> 1)) == 0) hi >>= 1;
-  int lo = 0;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    int count = 0;
+    for (int r = 0; r < kRegs; ++r) d[r] = m[r] = 0;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) count += __popcll(__ballot(w[j] <= (uint32_t)mid));
-    if (count >= k_eff)
-      hi = mid;
-    else
-      lo = mid + 1;
-  }
-  uint32_t m_lo = 0, m_hi = 0;
-  for_words<NW>([&](auto J) {  // Eq. 6-7
-    put_word<J.value>(__ballot(w[J.value] <= (uint32_t)lo), m_lo, m_hi);
-  });
-  if (lane < nw) {
-    out_desc[lane] = (static_cast<uint64_t>(d_hi) << 32) | d_lo;
-    out_mask[lane] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
+    for (int j = NW - 1; j >= 0; --j)
+      d[j / 32] = __builtin_amdgcn_alignbit(d[j / 32], (b[j] >> 24) - (a[j] >> 24), 31);
+    uint32_t w[NW];
+    pair_weights<NW>(a, b, centre, w);
+    const int T = kth_smallest<NW>(w, k_eff, guess);
+    const uint32_t minus_t1 = static_cast<uint32_t>(-T - 1);
+#pragma unroll
+    for (int j = NW - 1; j >= 0; --j)
+      m[j / 32] = __builtin_amdgcn_alignbit(m[j / 32], w[j] + minus_t1, 31);
+    if (NW * lane < n) {
+      store_lane_bits<NW>(out_desc, lane, d);
+      store_lane_bits<NW>(out_mask, lane, m);
+    }
+    return T;
+  } else {
+    uint32_t d_lo = 0, d_hi = 0, m_lo = 0, m_hi = 0;
+    for_words<NW>([&](auto J) {  // Eq. 3
+      put_word<J.value>(__ballot((a[J.value] >> 24) > (b[J.value] >> 24)), d_lo, d_hi);
+    });
+    uint32_t w[NW];
+    pair_weights<NW>(a, b, centre, w);
+    const int T = kth_smallest<NW>(w, k_eff, guess);
+    for_words<NW>([&](auto J) {  // Eq. 6-7
+      put_word<J.value>(__ballot(w[J.value] <= (uint32_t)T), m_lo, m_hi);
+    });
+    if (lane < n / 64) {
+      out_desc[lane] = (static_cast<uint64_t>(d_hi) << 32) | d_lo;
+      out_mask[lane] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
+    }
+    return T;
   }
 }
 
@@ -179,7 +303,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
                                                    int H, const DescribeConsts &c,
                                                    uint64_t *__restrict__ desc,
                                                    uint64_t *__restrict__ mask, int u0, int v0) {
-  const int radius = c.radius, pitch = c.pitch, nw = c.nw;
+  const int radius = c.radius, pitch = c.pitch, nw = c.nw, n = 64 * nw;
   const int rows = kDescTH + 2 * radius, cols = TW + 2 * radius;
   const int total = rows * cols;
   __syncthreads();  // the previous tile (persistent kernels) is done with LDS
@@ -208,29 +332,29 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // Byte offsets in LDS, relative to the centre, of this lane's pair samples.
-  // Words past nw (NW is nw rounded up to a power of two) get offset 0: their
-  // "pairs" compare the centre with itself, so their weight is 0 and they
-  // only shift the rank of the threshold by 64 per padded word.
+  // Byte offsets in LDS, relative to the centre, of this lane's pair samples
+  // (0 for padded pairs).
   int offp[NW], offq[NW];
   const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
     offp[j] = offq[j] = 0;
-    if (j < nw) {
-      const int32_t e = pat32[64 * j + lane];
+    const int i = pair_of<NW>(lane, j);
+    if (i < n) {
+      const int32_t e = pat32[i];
       const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
       const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
       offp[j] = 4 * (py * pitch + px);
       offq[j] = 4 * (qy * pitch + qx);
     }
   }
-  const int k_eff = c.k + 64 * (NW - nw);
+  const int k_eff = c.k + (64 * NW - n);
   __syncthreads();
 
   const char *lds = reinterpret_cast<const char *>(tile);
   constexpr int kRowsPerWave = kDescTH / (kDescThreads / 64);
   constexpr int kGroup = 4;  // pixels whose LDS addresses share one base
+  int guess = 64;            // threshold search start: the previous pixel's T
   for (int r = 0; r < kRowsPerWave; ++r) {
     const int ty = wave * kRowsPerWave + r, v = v0 + ty;
     if (v >= H) break;  // uniform
@@ -247,8 +371,9 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
       for (int t = 0; t < kGroup; ++t) {
         const int u = u0 + g + t;
         if (u >= W) break;  // uniform
-        describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, nw, k_eff,
-                           desc + ((size_t)v * W + u) * nw, mask + ((size_t)v * W + u) * nw);
+        guess = describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, n, k_eff, guess,
+                                   desc + ((size_t)v * W + u) * nw,
+                                   mask + ((size_t)v * W + u) * nw);
       }
     }
   }
@@ -724,12 +849,13 @@ __device__ __forceinline__ int owner(const int *start, int npairs, int t) {
   return lo;
 }
 
-// Next item of a queue for the whole workgroup (broadcast through LDS).
+// Next item of a queue for the whole workgroup (broadcast through LDS; the
+// value is uniform, so everything derived from it stays in scalar registers).
 __device__ __forceinline__ int take(int *counter, int *slot) {
   __syncthreads();  // everyone has read the previous value
   if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
   __syncthreads();
-  return *slot;
+  return __builtin_amdgcn_readfirstlane(*slot);
 }
 
 __global__ void k_batch_reset(int *counters) {
