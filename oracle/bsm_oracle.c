@@ -456,3 +456,91 @@ int oracle_match(const uint8_t *left, const uint8_t *right, int W, int H,
     free(maskL);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Right-reference matching and the left/right check (Section 3, the first  */
+/* part of the refinement step: two depth maps, one per reference view,     */
+/* classify each left pixel as valid or invalid).  Reading: the right map    */
+/* uses the same pattern, the right view's own mask, x_d = (u + d, v), and   */
+/* a pixel is valid when the two maps agree within 1 (the customary check   */
+/* of the cited two-view methods).                                          */
+/* ------------------------------------------------------------------------ */
+
+int oracle_match_right(const uint8_t *left, const uint8_t *right, int W, int H,
+                       int stride, const int8_t *pattern, int n, int k,
+                       int use_mask, int dmax, int32_t *disp, int16_t *cost)
+{
+    int nw = n / 64;
+    if (!valid_pattern_args(W, H, n, pattern) || stride < 3 * W || !left ||
+        !right || !disp || dmax < 1 || dmax > W || (use_mask && (k < 1 || k > n)))
+        return -1;
+    size_t npx = (size_t)W * H;
+    uint8_t *I = (uint8_t *)malloc(npx);
+    uint64_t *descL = (uint64_t *)malloc(npx * nw * sizeof(uint64_t));
+    uint64_t *descR = (uint64_t *)malloc(npx * nw * sizeof(uint64_t));
+    uint64_t *maskR = NULL;
+
+    oracle_luma(left, W, H, stride, I);
+    describe_from_luma(I, W, H, pattern, n, descL);
+    oracle_luma(right, W, H, stride, I);
+    describe_from_luma(I, W, H, pattern, n, descR);
+    if (use_mask) {
+        uint8_t *lab = (uint8_t *)malloc(npx * 3);
+        maskR = (uint64_t *)malloc(npx * nw * sizeof(uint64_t));
+        oracle_lab8(right, W, H, stride, lab);
+        mask_from_lab(lab, W, H, pattern, n, k, maskR, NULL);
+        free(lab);
+    }
+
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
+    for (int v = 0; v < H; v++)
+        for (int u = 0; u < W; u++) {
+            const uint64_t *BR = descR + ((size_t)v * W + u) * nw;
+            const uint64_t *M = maskR ? maskR + ((size_t)v * W + u) * nw : NULL;
+            int best_d = 0, best_c = 0;
+            for (int d = 0; d < dmax; d++) {
+                int c = ORACLE_INVALID_COST;
+                if (u + d <= W - 1) {
+                    const uint64_t *BL = descL + ((size_t)v * W + (u + d)) * nw;
+                    c = 0;
+                    for (int j = 0; j < nw; j++) {
+                        uint64_t x = BR[j] ^ BL[j];
+                        if (M)
+                            x &= M[j];
+                        c += __builtin_popcountll(x);
+                    }
+                }
+                if (cost)
+                    cost[((size_t)d * H + v) * W + u] = (int16_t)c;
+                if (d == 0 || c < best_c) {
+                    best_c = c;
+                    best_d = d;
+                }
+            }
+            disp[(size_t)v * W + u] = best_d;
+        }
+
+    free(I);
+    free(descL);
+    free(descR);
+    free(maskR);
+    return 0;
+}
+
+int oracle_lr_check(const int32_t *dL, const int32_t *dR, int W, int H,
+                    int tol, int32_t *out)
+{
+    if (W < 1 || H < 1 || tol < 0 || !dL || !dR || !out)
+        return -1;
+    for (int v = 0; v < H; v++)
+        for (int u = 0; u < W; u++) {
+            int d = dL[(size_t)v * W + u];
+            int ok = 0;
+            if (d >= 0 && u - d >= 0) {
+                int e = d - dR[(size_t)v * W + (u - d)];
+                ok = (e < 0 ? -e : e) <= tol;
+            }
+            out[(size_t)v * W + u] = ok ? d : -1;
+        }
+    return 0;
+}

@@ -78,6 +78,21 @@ int oracle_match(const uint8_t *left, const uint8_t *right, int W, int H,
                  int stride, const int8_t *pattern, int n, int k,
                  int use_mask, int dmax, int32_t *disp, int16_t *cost);
 
+/* Right-reference matching, the second depth map of the left/right check
+ * that opens the refinement step of Section 3: the right view is the
+ * reference, pixel (u, v) of the right view is compared with (u + d, v) of
+ * the left view, the mask is the right view's own (Eq. 5-7 on the right
+ * image), a partner outside the image (u + d > W - 1) has no cost (32767),
+ * ties take the lowest d.  cost may be NULL. */
+int oracle_match_right(const uint8_t *left, const uint8_t *right, int W, int H,
+                       int stride, const int8_t *pattern, int n, int k,
+                       int use_mask, int dmax, int32_t *disp, int16_t *cost);
+
+/* Left/right consistency check (Section 3, refinement step): out = dL
+ * where |dL(u, v) - dR(u - dL(u, v), v)| <= tol, else -1. */
+int oracle_lr_check(const int32_t *dL, const int32_t *dR, int W, int H,
+                    int tol, int32_t *out);
+
 #ifdef __cplusplus
 }
 #endif

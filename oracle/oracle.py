@@ -55,6 +55,10 @@ def load():
     lib.oracle_match.argtypes = [u8p, u8p, ci, ci, ci, i8p, ci, ci, ci, ci,
                                  i32p, i16p]
     lib.oracle_match.restype = ci
+    lib.oracle_match_right.argtypes = [u8p, u8p, ci, ci, ci, i8p, ci, ci, ci, ci, i32p, i16p]
+    lib.oracle_match_right.restype = ci
+    lib.oracle_lr_check.argtypes = [i32p, i32p, ci, ci, ci, i32p]
+    lib.oracle_lr_check.restype = ci
     _lib = lib
     return lib
 
@@ -205,3 +209,33 @@ def match(left, right, pattern, dmax, k=None, use_mask=True, want_cost=False):
                                _p(pattern, C.c_int8), n, k, 1 if use_mask else 0, dmax,
                                _p(disp, C.c_int32), _p(cost, C.c_int16)), "match")
     return disp, cost
+
+
+def match_right(left, right, pattern, dmax, k=None, use_mask=True, want_cost=False):
+    """Right-reference matching: (disp int32 [H][W] of the right view,
+    cost int16 [dmax][H][W] or None), partner (u + d, v) in the left view."""
+    left, W, H, st = _img(left)
+    right, W2, H2, _ = _img(right)
+    if (W2, H2) != (W, H):
+        raise ValueError("left and right must have the same shape")
+    pattern, n = _pat(pattern)
+    k = n // 4 if k is None else int(k)
+    disp = np.zeros((H, W), np.int32)
+    cost = np.zeros((dmax, H, W), np.int16) if want_cost else None
+    _check(load().oracle_match_right(_p(left, C.c_uint8), _p(right, C.c_uint8), W, H, st,
+                                     _p(pattern, C.c_int8), n, k, 1 if use_mask else 0, dmax,
+                                     _p(disp, C.c_int32), _p(cost, C.c_int16)), "match_right")
+    return disp, cost
+
+
+def lr_check(dL, dR, tol=1):
+    """dL where |dL(u) - dR(u - dL(u))| <= tol, else -1."""
+    dL = np.ascontiguousarray(dL, np.int32)
+    dR = np.ascontiguousarray(dR, np.int32)
+    if dL.shape != dR.shape or dL.ndim != 2:
+        raise ValueError("dL and dR must be [H][W] of the same shape")
+    H, W = dL.shape
+    out = np.zeros((H, W), np.int32)
+    _check(load().oracle_lr_check(_p(dL, C.c_int32), _p(dR, C.c_int32), W, H, int(tol),
+                                  _p(out, C.c_int32)), "lr_check")
+    return out
