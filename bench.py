@@ -33,6 +33,8 @@ WORKLOADS = {
     2: "1400x1100 slanted planes + radiometric change, dmax 256, n 1024, S 31",
     3: "64 uneven slanted-plane pairs (W 320-1920, H 240-1080, dmax 32-256), n 1024, S 31",
     4: "serving: Poisson arrivals of the 64 uneven pairs, n 1024, S 31, 32 GiB admission cap",
+    5: "descriptor-length sweep: 1400x1100 slanted planes + radiometric change, dmax 256, S 31, "
+       "n 64..4096",
 }
 
 
@@ -250,6 +252,90 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_nsweep(args):
+    """Throughput against descriptor length n on the 1400x1100, dmax 256
+    pair (the paper's Section 4.3 studies n; its Fig. 3 reports quality,
+    here the point is speed): per n, the whole path per pair and the split
+    into describe (both views) and cost+WTA, timed with HIP events."""
+    import torch
+
+    from paper_1402_2020_amd import _bsm, synth
+    scene = synth.config_scene(2)
+    H, W = scene.left.shape[:2]
+    dmax, S = 256, 31
+    sigma = 4.0 * S / 26
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(scene.left).to(dev)
+    R = torch.from_numpy(scene.right).to(dev)
+    stream = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, 10))
+    rows = []
+    for n in args.nbits:
+        pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
+        ctx = _bsm.Context(n, S, sigma, pattern=pat, device=0)
+        disp = torch.empty((H, W), dtype=torch.int32, device=dev)
+        for _ in range(max(1, args.warmup)):
+            ctx.match(L, R, dmax, disp=disp)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.match(L, R, dmax, disp=disp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        # split: descriptors of both views vs cost + WTA
+        descL, maskL = ctx.describe(L, with_mask=True)
+        descR, _ = ctx.describe(R)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.describe(L, with_mask=True)
+            ctx.describe(R)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_desc = e0.elapsed_time(e1) / steps
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.cost_wta(descL, maskL, descR, dmax)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_cost = e0.elapsed_time(e1) / steps
+        evals = W * H * dmax
+        rows.append({"n_bits": n, "ms_per_pair": round(ms, 4), "evals_per_s": evals / (ms / 1e3),
+                     "ms_describe_both_views": round(ms_desc, 4), "ms_cost_wta": round(ms_cost, 4),
+                     "cost_wta_frac_of_alu_peak": evals * (n / 16 + 1) / (ms_cost / 1e3) /
+                     ALU_PEAK_OPS})
+        print(json.dumps({"progress": "nsweep", **rows[-1]}), flush=True)
+        ctx.close()
+    # least-squares slope of time against n (the paper states linear cost in n)
+    import numpy as np
+    ns = np.array([r["n_bits"] for r in rows], float)
+    ts = np.array([r["ms_per_pair"] for r in rows], float)
+    slope, icpt = np.polyfit(ns, ts, 1) if len(rows) > 1 else (float("nan"), float("nan"))
+    top = max(rows, key=lambda r: r["n_bits"])
+    out = {
+        "metric": "disparity evals/sec (W*H*dmax/s)",
+        "value": top["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(1, args.warmup),
+        "ms_per_step": top["ms_per_pair"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded scene generator; Middlebury stand-in)",
+        "config": {"workload": WORKLOADS[5], "W": W, "H": H, "dmax": dmax, "window": S,
+                   "n_bits": list(args.nbits)},
+        "sweep": rows,
+        "linear_fit_ms": {"per_bit": slope, "intercept": icpt},
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources_hash():
     h = hashlib.sha256()
     for name in ("bsm_kernels.hip",):
@@ -299,6 +385,8 @@ def main():
                     help="serving workload: seconds of arrivals per rate")
     ap.add_argument("--rates", type=int, nargs="+", default=[50, 200, 800],
                     help="serving workload: arrival rates, pairs/s")
+    ap.add_argument("--nbits", type=int, nargs="+", default=[64, 128, 256, 512, 1024, 2048, 4096],
+                    help="descriptor-length sweep: the n values")
     ap.add_argument("--max-group", type=int, default=0,
                     help="serving workload: most pairs per group (0: library default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -333,6 +421,8 @@ def main():
         return bench_batch(args)
     if cfg == 4:
         return bench_serve(args)
+    if cfg == 5:
+        return bench_nsweep(args)
     p = synth.CONFIG_PARAMS[cfg]
     scene = synth.config_scene(cfg)
     H, W = scene.left.shape[:2]

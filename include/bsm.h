@@ -176,6 +176,29 @@ bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                      int32_t W, int32_t H, int32_t stride, int32_t dmax,
                      int32_t *disp, int16_t *cost, void *hip_stream);
 
+/* Right-reference matching: the second depth map of the left/right check
+ * that opens the refinement step of Section 3.  The right view is the
+ * reference: pixel (u, v) of the right view is compared with (u + d, v) of
+ * the left view, with the right view's own mask (Eq. 5-7 on the right
+ * image); volume entries with u + d > W - 1 hold 32767; ties take the
+ * lowest d.  Same arguments, buffers and errors as bsm_match; disp and cost
+ * are indexed by right-view pixels.  Runs the left-reference kernels on the
+ * horizontally mirrored views with the mirrored pattern and reverses the
+ * results' rows. */
+bsm_status bsm_match_right(bsm_ctx *ctx, const uint8_t *left,
+                           const uint8_t *right, int32_t W, int32_t H,
+                           int32_t stride, int32_t dmax, int32_t *disp,
+                           int16_t *cost, void *hip_stream);
+
+/* Left/right consistency check (Section 3, refinement step): out(u, v) =
+ * dL(u, v) where |dL(u, v) - dR(u - dL(u, v), v)| <= tol (the pixel is
+ * valid), else -1 (invalid; also when u - dL(u, v) < 0).  disp_left,
+ * disp_right, out: device int32 [H][W], 4-byte aligned; out may be
+ * disp_left (in place) but not disp_right.  tol >= 0 (1 is customary). */
+bsm_status bsm_lr_check(bsm_ctx *ctx, const int32_t *disp_left,
+                        const int32_t *disp_right, int32_t W, int32_t H,
+                        int32_t tol, int32_t *out, void *hip_stream);
+
 /* Many pairs of uneven size and dmax at once.  The tiles of all pairs go
  * into device work queues (largest pair first) served by one persistent
  * kernel per stage (colour, describe+mask, describe, cost+WTA); the four

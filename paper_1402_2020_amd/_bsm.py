@@ -19,6 +19,7 @@ INVALID_COST = 32767
 # Every symbol include/bsm.h declares.
 EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
            "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
+           "bsm_match_right", "bsm_lr_check",
            "bsm_match_batch", "bsm_get_tuning", "bsm_set_tuning", "bsm_autotune",
            "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain", "bsm_serve_stats")
 
@@ -99,6 +100,8 @@ def load():
         "bsm_describe_packed": ([vp, vp, i32, i32, vp, vp, vp], st),
         "bsm_cost_wta": ([vp, vp, vp, vp, i32, i32, i32, vp, vp, vp], st),
         "bsm_match": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
+        "bsm_match_right": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
+        "bsm_lr_check": ([vp, vp, vp, i32, i32, i32, vp, vp], st),
         "bsm_match_batch": ([vp, C.POINTER(Pair), i32, vp], st),
         "bsm_get_tuning": ([vp, C.POINTER(Tuning)], st),
         "bsm_set_tuning": ([vp, C.POINTER(Tuning)], st),
@@ -183,6 +186,14 @@ def bsm_cost_wta(ctx, descL, maskL, descR, W, H, dmax, disp, cost, stream):
 
 def bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
     return load().bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream)
+
+
+def bsm_match_right(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
+    return load().bsm_match_right(ctx, left, right, W, H, stride, dmax, disp, cost, stream)
+
+
+def bsm_lr_check(ctx, disp_left, disp_right, W, H, tol, out, stream):
+    return load().bsm_lr_check(ctx, disp_left, disp_right, W, H, tol, out, stream)
 
 
 def bsm_match_batch(ctx, pairs, stream):
@@ -333,6 +344,32 @@ class Context:
         _check(bsm_match(self.h, _ptr(left), _ptr(right), W, H, st, dmax, _ptr(disp),
                          _ptr(cost), _stream(stream)), "bsm_match")
         return disp, cost
+
+    def match_right(self, left, right, dmax, want_cost=False, disp=None, cost=None, stream=None):
+        """Right-reference matching: disparities of the right view's pixels
+        (partner (u + d, v) in the left view)."""
+        import torch
+        left, W, H, st = self._img(left)
+        right, W2, H2, _ = self._img(right)
+        if (W2, H2) != (W, H):
+            raise ValueError("left and right must have the same shape")
+        if disp is None:
+            disp = torch.empty((H, W), dtype=torch.int32, device=left.device)
+        if cost is None and want_cost:
+            cost = torch.empty((dmax, H, W), dtype=torch.int16, device=left.device)
+        _check(bsm_match_right(self.h, _ptr(left), _ptr(right), W, H, st, dmax, _ptr(disp),
+                               _ptr(cost), _stream(stream)), "bsm_match_right")
+        return disp, cost
+
+    def lr_check(self, disp_left, disp_right, tol=1, out=None, stream=None):
+        """disp_left where the two maps agree within tol, else -1."""
+        import torch
+        H, W = disp_left.shape
+        if out is None:
+            out = torch.empty_like(disp_left)
+        _check(bsm_lr_check(self.h, _ptr(disp_left), _ptr(disp_right), W, H, tol, _ptr(out),
+                            _stream(stream)), "bsm_lr_check")
+        return out
 
     def tuning(self):
         return bsm_get_tuning(self.h).as_dict()

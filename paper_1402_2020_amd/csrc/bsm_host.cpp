@@ -280,32 +280,53 @@ size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H) {
 }
 
 // The whole hot path of one pair on stream s; `scratch` holds
-// match_scratch_bytes(W, H).
+// match_scratch_bytes(W, H).  With right_reference the right view is the
+// reference (partner (u + d, v) in the left view, the right view's mask):
+// that is left-reference matching of the mirrored pair (mirrored right view
+// as reference, mirrored left view as the other) with the mirrored pattern,
+// whose results are reversed back row by row.
 bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                            int W, int H, int stride, int dmax, int32_t *disp,
-                           int16_t *cost, void *scratch, hipStream_t s) {
+                           int16_t *cost, void *scratch, hipStream_t s, bool right_reference) {
   size_t px = (size_t)W * H;
   char *base = static_cast<char *>(scratch);
   uint32_t *packed = reinterpret_cast<uint32_t *>(base);
   size_t desc_bytes = round_up(px * ctx->nw * 8, 256);
-  uint64_t *descL = reinterpret_cast<uint64_t *>(base + round_up(px * 4, 256));
-  uint64_t *maskL = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(descL) + desc_bytes);
-  uint64_t *descR = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(maskL) + desc_bytes);
+  uint64_t *descA = reinterpret_cast<uint64_t *>(base + round_up(px * 4, 256));
+  uint64_t *maskA = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(descA) + desc_bytes);
+  uint64_t *descB = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(maskA) + desc_bytes);
   const bool m = ctx->use_mask != 0;
+  const DeviceTables t = right_reference ? mirrored_tables(ctx) : ctx->dt;
+  const uint8_t *ref = right_reference ? right : left;
+  const uint8_t *other = right_reference ? left : right;
+  const int mirror = right_reference ? 1 : 0;
   hipError_t e;
-  if ((e = launch_color(left, W, H, stride, packed, m, ctx->dt, s)) != hipSuccess)
-    return device_fail(ctx, e, "colour pre-pass (left)");
-  if ((e = launch_describe(packed, W, H, ctx->dt, descL, m ? maskL : nullptr, s)) != hipSuccess)
-    return device_fail(ctx, e, "describe (left)");
-  if ((e = launch_color(right, W, H, stride, packed, 0, ctx->dt, s)) != hipSuccess)
-    return device_fail(ctx, e, "colour pre-pass (right)");
-  if ((e = launch_describe(packed, W, H, ctx->dt, descR, nullptr, s)) != hipSuccess)
-    return device_fail(ctx, e, "describe (right)");
-  if ((e = launch_cost_wta(descL, m ? maskL : nullptr, descR, W, H, ctx->nw, dmax, disp, cost,
-                           ctx->dt, s)) !=
-      hipSuccess)
+  if ((e = launch_color(ref, W, H, stride, packed, m, mirror, t, s)) != hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass (reference view)");
+  if ((e = launch_describe(packed, W, H, t, descA, m ? maskA : nullptr, s)) != hipSuccess)
+    return device_fail(ctx, e, "describe (reference view)");
+  if ((e = launch_color(other, W, H, stride, packed, 0, mirror, t, s)) != hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass (other view)");
+  if ((e = launch_describe(packed, W, H, t, descB, nullptr, s)) != hipSuccess)
+    return device_fail(ctx, e, "describe (other view)");
+  if ((e = launch_cost_wta(descA, m ? maskA : nullptr, descB, W, H, ctx->nw, dmax, disp, cost, t,
+                           s)) != hipSuccess)
     return device_fail(ctx, e, "cost + WTA");
+  if (right_reference) {
+    if ((e = launch_reverse_rows(disp, W, H, s)) != hipSuccess ||
+        (cost && (e = launch_reverse_rows(cost, W, dmax * H, s)) != hipSuccess))
+      return device_fail(ctx, e, "mirroring results back");
+  }
   return BSM_OK;
+}
+
+DeviceTables mirrored_tables(const bsm_ctx *ctx) {
+  DeviceTables t = ctx->dt;
+  t.pattern = ctx->d_pattern_m;
+  t.right_offs = ctx->d_right_offs_m;
+  t.left_pitch16 = ctx->left_pitch16_m;
+  t.left_pitch32 = ctx->left_pitch32_m;
+  return t;
 }
 
 }  // namespace bsm
@@ -384,6 +405,19 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
     const int8_t *o = &ctx->pattern[4 * i];
     right_offs[i] = make_int2(o[1] * right_pitch + o[0], o[3] * right_pitch + o[2]);
   }
+  // The same for the mirrored pattern (right-reference matching).
+  std::vector<int8_t> mirrored(ctx->pattern);
+  for (int i = 0; i < ctx->n; ++i) {
+    mirrored[4 * i] = static_cast<int8_t>(-mirrored[4 * i]);
+    mirrored[4 * i + 2] = static_cast<int8_t>(-mirrored[4 * i + 2]);
+  }
+  ctx->left_pitch16_m = choose_left_pitch(mirrored.data(), ctx->n, describe_left_cols(radius, 16));
+  ctx->left_pitch32_m = choose_left_pitch(mirrored.data(), ctx->n, describe_left_cols(radius, 32));
+  std::vector<int2> right_offs_m(ctx->n);
+  for (int i = 0; i < ctx->n; ++i) {
+    const int8_t *o = &mirrored[4 * i];
+    right_offs_m[i] = make_int2(o[1] * right_pitch + o[0], o[3] * right_pitch + o[2]);
+  }
 
   DeviceGuard g(hip_device);
   if (g.err() != hipSuccess) return device_fail(nullptr, g.err(), "hipSetDevice");
@@ -391,7 +425,9 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
   if ((e = hipMalloc(&ctx->d_pattern, ctx->pattern.size())) != hipSuccess ||
       (e = hipMalloc(&ctx->d_lin, 256 * sizeof(uint16_t))) != hipSuccess ||
       (e = hipMalloc(&ctx->d_f, 65536 * sizeof(uint16_t))) != hipSuccess ||
-      (e = hipMalloc(&ctx->d_right_offs, right_offs.size() * sizeof(int2))) != hipSuccess) {
+      (e = hipMalloc(&ctx->d_right_offs, right_offs.size() * sizeof(int2))) != hipSuccess ||
+      (e = hipMalloc(&ctx->d_pattern_m, mirrored.size())) != hipSuccess ||
+      (e = hipMalloc(&ctx->d_right_offs_m, right_offs_m.size() * sizeof(int2))) != hipSuccess) {
     bsm_destroy(ctx.release());
     return device_fail(nullptr, e, "allocating context tables");
   }
@@ -402,6 +438,10 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
       (e = hipMemcpy(ctx->d_f, ctx->tables.f.data(), 65536 * sizeof(uint16_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(ctx->d_right_offs, right_offs.data(), right_offs.size() * sizeof(int2),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(ctx->d_pattern_m, mirrored.data(), mirrored.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(ctx->d_right_offs_m, right_offs_m.data(), right_offs_m.size() * sizeof(int2),
                      hipMemcpyHostToDevice)) != hipSuccess) {
     bsm_destroy(ctx.release());
     return device_fail(nullptr, e, "uploading context tables");
@@ -433,6 +473,8 @@ void bsm_destroy(bsm_ctx *ctx) {
   if (ctx->d_lin) (void)hipFree(ctx->d_lin);
   if (ctx->d_f) (void)hipFree(ctx->d_f);
   if (ctx->d_right_offs) (void)hipFree(ctx->d_right_offs);
+  if (ctx->d_pattern_m) (void)hipFree(ctx->d_pattern_m);
+  if (ctx->d_right_offs_m) (void)hipFree(ctx->d_right_offs_m);
   delete ctx;  // scratch buffers are released with the device still current
 }
 
@@ -461,7 +503,7 @@ bsm_status bsm_color(bsm_ctx *ctx, const uint8_t *img, int32_t W, int32_t H, int
     return fail(BSM_EINVAL, "packed output must be a 4-byte aligned device pointer");
   DeviceGuard g(ctx->device);
   if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
-  hipError_t e = launch_color(img, W, H, stride, packed, want_lab ? 1 : 0, ctx->dt,
+  hipError_t e = launch_color(img, W, H, stride, packed, want_lab ? 1 : 0, 0, ctx->dt,
                               static_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? BSM_OK : device_fail(ctx, e, "colour pre-pass");
 }
@@ -480,7 +522,8 @@ bsm_status bsm_describe(bsm_ctx *ctx, const uint8_t *img, int32_t W, int32_t H, 
   hipError_t e;
   void *buf = ctx->describe_scratch.acquire((size_t)W * H * 4, s, &e);
   if (!buf) return device_fail(ctx, e, "describe scratch");
-  if ((e = launch_color(img, W, H, stride, static_cast<uint32_t *>(buf), mask != nullptr, ctx->dt, s)) !=
+  if ((e = launch_color(img, W, H, stride, static_cast<uint32_t *>(buf), mask != nullptr, 0, ctx->dt,
+                        s)) !=
       hipSuccess)
     return device_fail(ctx, e, "colour pre-pass");
   if ((e = launch_describe(static_cast<uint32_t *>(buf), W, H, ctx->dt, desc, mask, s)) != hipSuccess)
@@ -559,8 +602,9 @@ bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *in) {
   return BSM_OK;
 }
 
-bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, int32_t W, int32_t H,
-                     int32_t stride, int32_t dmax, int32_t *disp, int16_t *cost, void *hip_stream) {
+static bsm_status match_entry(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, int32_t W,
+                              int32_t H, int32_t stride, int32_t dmax, int32_t *disp,
+                              int16_t *cost, void *hip_stream, bool right_reference) {
   clear_error();
   bsm_status st;
   if ((st = check_alive(ctx)) != BSM_OK) return st;
@@ -575,10 +619,43 @@ bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, in
   hipError_t e;
   void *buf = ctx->match_scratch.acquire(match_scratch_bytes(ctx, W, H), s, &e);
   if (!buf) return device_fail(ctx, e, "match scratch");
-  st = match_on_stream(ctx, left, right, W, H, stride, dmax, disp, cost, buf, s);
+  st = match_on_stream(ctx, left, right, W, H, stride, dmax, disp, cost, buf, s, right_reference);
   if (st != BSM_OK) return st;
   if ((e = ctx->match_scratch.release(s)) != hipSuccess)
     return device_fail(ctx, e, "match scratch event");
+  return BSM_OK;
+}
+
+bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, int32_t W, int32_t H,
+                     int32_t stride, int32_t dmax, int32_t *disp, int16_t *cost, void *hip_stream) {
+  return match_entry(ctx, left, right, W, H, stride, dmax, disp, cost, hip_stream, false);
+}
+
+bsm_status bsm_match_right(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right, int32_t W,
+                           int32_t H, int32_t stride, int32_t dmax, int32_t *disp, int16_t *cost,
+                           void *hip_stream) {
+  return match_entry(ctx, left, right, W, H, stride, dmax, disp, cost, hip_stream, true);
+}
+
+bsm_status bsm_lr_check(bsm_ctx *ctx, const int32_t *disp_left, const int32_t *disp_right,
+                        int32_t W, int32_t H, int32_t tol, int32_t *out, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide)
+    return fail(BSM_EINVAL, "image size %d x %d out of [1, %d]", W, H, kMaxSide);
+  if (tol < 0) return fail(BSM_EINVAL, "tol must be >= 0");
+  if (!disp_left || !disp_right || !out)
+    return fail(BSM_EINVAL, "disp_left, disp_right and out must not be NULL");
+  if ((reinterpret_cast<uintptr_t>(disp_left) | reinterpret_cast<uintptr_t>(disp_right) |
+       reinterpret_cast<uintptr_t>(out)) & 3u)
+    return fail(BSM_EINVAL, "disparity maps must be 4-byte aligned");
+  if (out == disp_right) return fail(BSM_EINVAL, "out must not alias disp_right");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipError_t e = launch_lr_check(disp_left, disp_right, W, H, tol, out,
+                                 static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return device_fail(ctx, e, "left/right check");
   return BSM_OK;
 }
 

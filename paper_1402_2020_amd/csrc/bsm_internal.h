@@ -105,8 +105,13 @@ struct BatchLaunch {
 
 // ---- kernel launchers (bsm_kernels.hip) -----------------------------------
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride,
-                        uint32_t *packed, int want_lab, const DeviceTables &t,
-                        hipStream_t s);
+                        uint32_t *packed, int want_lab, int mirror,
+                        const DeviceTables &t, hipStream_t s);
+// In-place reversal of each of `rows` rows of W elements.
+hipError_t launch_reverse_rows(int32_t *data, int W, int rows, hipStream_t s);
+hipError_t launch_reverse_rows(int16_t *data, int W, int rows, hipStream_t s);
+hipError_t launch_lr_check(const int32_t *dL, const int32_t *dR, int W, int H, int tol,
+                           int32_t *out, hipStream_t s);
 hipError_t launch_describe(const uint32_t *packed, int W, int H,
                            const DeviceTables &t, uint64_t *desc,
                            uint64_t *mask, hipStream_t s);
@@ -171,6 +176,12 @@ struct bsm_ctx {
   uint16_t *d_f = nullptr;
   int2 *d_right_offs = nullptr;
   bsm::DeviceTables dt{};
+  // The pattern mirrored horizontally (x offsets negated) and its LDS
+  // layouts: right-reference matching runs the left-reference kernels on
+  // the mirrored views with it.
+  int8_t *d_pattern_m = nullptr;
+  int2 *d_right_offs_m = nullptr;
+  int left_pitch16_m = 0, left_pitch32_m = 0;
   std::mutex tune_mu;  // guards dt.tune between its setters and the serving thread
   bsm::Scratch describe_scratch;  // packed colour plane of bsm_describe
   bsm::Scratch match_scratch;     // planes + descriptors of bsm_match
@@ -193,9 +204,11 @@ bsm_status validate_dmax(int W, int dmax);
 bool aligned8(const void *p);
 bool aligned16(const void *p);
 size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H);
+// The context's tables with the mirrored pattern in place of the pattern.
+DeviceTables mirrored_tables(const bsm_ctx *ctx);
 bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left,
                            const uint8_t *right, int W, int H, int stride,
                            int dmax, int32_t *disp, int16_t *cost,
-                           void *scratch, hipStream_t s);
+                           void *scratch, hipStream_t s, bool right_reference = false);
 double now_seconds();
 }  // namespace bsm

@@ -38,11 +38,13 @@ __device__ __forceinline__ uint32_t clamp_u8(int32_t x) {
   return static_cast<uint32_t>(x < 0 ? 0 : (x > 255 ? 255 : x));
 }
 
+// mirror != 0 writes pixel u of a row to column W - 1 - u (the horizontally
+// mirrored view, used for right-reference matching).
 __device__ __forceinline__ void color_tile(const uint8_t *__restrict__ img, int W, int H,
                                            int stride, uint32_t *__restrict__ out,
                                            const uint16_t *__restrict__ lin,
                                            const uint16_t *__restrict__ ftab, const Mq &mq,
-                                           int want_lab, int u0, int v0) {
+                                           int want_lab, int mirror, int u0, int v0) {
   const int u = u0 + (threadIdx.x % kColorTX);
   if (u >= W) return;
 #pragma unroll
@@ -63,7 +65,7 @@ __device__ __forceinline__ void color_tile(const uint8_t *__restrict__ img, int 
       const uint32_t b8 = clamp_u8(128 + nearest_div(200 * (int64_t)(fy - fz), 65535));
       word |= L8 | (a8 << 8) | (b8 << 16);
     }
-    out[(size_t)v * W + u] = word;
+    out[(size_t)v * W + (mirror ? W - 1 - u : u)] = word;
   }
 }
 
@@ -72,9 +74,40 @@ __global__ __launch_bounds__(kColorThreads) void k_color(const uint8_t *__restri
                                                          uint32_t *__restrict__ out,
                                                          const uint16_t *__restrict__ lin,
                                                          const uint16_t *__restrict__ ftab, Mq mq,
-                                                         int want_lab) {
-  color_tile(img, W, H, stride, out, lin, ftab, mq, want_lab, blockIdx.x * kColorTX,
+                                                         int want_lab, int mirror) {
+  color_tile(img, W, H, stride, out, lin, ftab, mq, want_lab, mirror, blockIdx.x * kColorTX,
              blockIdx.y * kColorTY);
+}
+
+// Reverses every row of a [rows][W] array in place (maps results of the
+// mirrored frame back to image columns).
+template <typename T>
+__global__ __launch_bounds__(256) void k_reverse_rows(T *__restrict__ data, int W, int rows) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y + blockIdx.z * 65535;
+  if (r >= rows || u >= W / 2) return;
+  T *row = data + (size_t)r * W;
+  const T a = row[u], b = row[W - 1 - u];
+  row[u] = b;
+  row[W - 1 - u] = a;
+}
+
+// Left/right consistency check of two disparity maps (the first part of the
+// refinement step of Section 3): dL where |dL(u) - dR(u - dL(u))| <= tol,
+// else -1.
+__global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL,
+                                                  const int32_t *__restrict__ dR, int W, int H,
+                                                  int tol, int32_t *__restrict__ out) {
+  const int u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y;
+  if (u >= W || v >= H) return;
+  const size_t row = (size_t)v * W;
+  const int d = dL[row + u];
+  bool ok = false;
+  if (d >= 0 && u - d >= 0) {
+    const int e = d - dR[row + u - d];
+    ok = (e < 0 ? -e : e) <= tol;
+  }
+  out[row + u] = ok ? d : -1;
 }
 
 // ===========================================================================
@@ -877,7 +910,8 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
     const int tx = (p.W + kColorTX - 1) / kColorTX, ty = (p.H + kColorTY - 1) / kColorTY;
     const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
     color_tile(view ? p.right : p.left, p.W, p.H, p.stride, view ? p.packedR : p.packedL, lin,
-               ftab, mq, view == 0 && use_mask, (tile % tx) * kColorTX, (tile / tx) * kColorTY);
+               ftab, mq, view == 0 && use_mask, 0, (tile % tx) * kColorTX,
+               (tile / tx) * kColorTY);
   }
 }
 
@@ -1136,10 +1170,34 @@ void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_
 bool batch_supported(int nw) { return nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16; }
 
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride, uint32_t *packed,
-                        int want_lab, const DeviceTables &t, hipStream_t s) {
+                        int want_lab, int mirror, const DeviceTables &t, hipStream_t s) {
   dim3 grid((W + kColorTX - 1) / kColorTX, (H + kColorTY - 1) / kColorTY);
   hipLaunchKernelGGL(k_color, grid, dim3(kColorThreads), 0, s, img, W, H, stride, packed, t.lin,
-                     t.f, t.mq, want_lab);
+                     t.f, t.mq, want_lab, mirror);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reverse_rows_t(T *data, int W, int rows, hipStream_t s) {
+  if (W < 2 || rows < 1) return hipSuccess;
+  const int ry = rows < 65535 ? rows : 65535;
+  dim3 grid((W / 2 + 255) / 256, ry, (rows + 65534) / 65535);
+  hipLaunchKernelGGL(k_reverse_rows<T>, grid, dim3(256), 0, s, data, W, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse_rows(int32_t *data, int W, int rows, hipStream_t s) {
+  return launch_reverse_rows_t(data, W, rows, s);
+}
+
+hipError_t launch_reverse_rows(int16_t *data, int W, int rows, hipStream_t s) {
+  return launch_reverse_rows_t(data, W, rows, s);
+}
+
+hipError_t launch_lr_check(const int32_t *dL, const int32_t *dR, int W, int H, int tol,
+                           int32_t *out, hipStream_t s) {
+  dim3 grid((W + 255) / 256, H);
+  hipLaunchKernelGGL(k_lr_check, grid, dim3(256), 0, s, dL, dR, W, H, tol, out);
   return hipGetLastError();
 }
 
