@@ -807,57 +807,119 @@ __global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict
 }
 
 // ===========================================================================
-// Cost + WTA for any n = 64 nw bits, nw <= 64 (the general fallback).  Lanes
-// over disparities; the left descriptor and mask of the current pixel are
-// wave-uniform (scalar loads); the right descriptors of the window sit in
-// LDS word-major.
+// Cost + WTA for any n = 64 nw bits (nw outside the register-resident
+// kernel's set, up to n = 4096).  Same tiling and diagonal reuse as above
+// (one wave per row tile of 128 pixels, lane l owns a = u0 + 2l and b = a +
+// 1, B_R(a - d) serves (a, d) and (b, d + 1)), but the words of the
+// descriptors are walked in chunks of kChunkWords: for each chunk of
+// kChunkD disparities the lane keeps the partial costs of its two pixels in
+// registers and adds one chunk of words at a time, with the left words of
+// its pixels loaded from global memory and the right words of the window
+// staged in LDS as [word][parity][pixel / 2].  Words past nw are zero.
 // ===========================================================================
-constexpr int kGenTX = 32;
-constexpr int kGenWin = kGenTX + 63;  // right pixels per window
+constexpr int kChunkD = 32, kChunkWords = 4;
+constexpr int kChunkP = kCostTX - 1 + kChunkD;      // window pixels
+constexpr int kChunkHP = (kChunkP + 1) / 2 + 1;     // pixels per parity half
+constexpr size_t kChunkLds = (size_t)kChunkWords * 2 * kChunkHP * sizeof(uint64_t);
 
-__global__ __launch_bounds__(64) void k_cost_wta_generic(const uint64_t *__restrict__ descL,
+__device__ __forceinline__ uint32_t masked_cost1(uint64_t bl, uint64_t m, uint64_t br, bool use_mask,
+                                                 uint32_t c) {
+  const uint32_t lo = use_mask ? __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(bl),
+                                                             static_cast<uint32_t>(br),
+                                                             static_cast<uint32_t>(m), kXorAnd)
+                               : static_cast<uint32_t>(bl ^ br);
+  const uint32_t hi = use_mask ? __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(bl >> 32),
+                                                             static_cast<uint32_t>(br >> 32),
+                                                             static_cast<uint32_t>(m >> 32), kXorAnd)
+                               : static_cast<uint32_t>((bl ^ br) >> 32);
+  return bcnt_acc(hi, bcnt_acc(lo, c));
+}
+
+template <bool MASK, bool VOL>
+__global__ __launch_bounds__(64) void k_cost_wta_chunked(const uint64_t *__restrict__ descL,
                                                          const uint64_t *__restrict__ maskL,
                                                          const uint64_t *__restrict__ descR, int W,
                                                          int H, int nw, int dmax,
                                                          int32_t *__restrict__ disp,
                                                          int16_t *__restrict__ cost) {
-  extern __shared__ uint64_t gwin[];  // [nw][kGenWin]
+  extern __shared__ uint64_t cwin[];  // [kChunkWords][2][kChunkHP]
+  const int tiles = (W + kCostTX - 1) / kCostTX;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / tiles);
+  if (v >= H) return;  // whole block
+  const int u0 = (slot % tiles) * kCostTX;
   const int lane = threadIdx.x;
-  const int v = blockIdx.y;
-  const int u0 = blockIdx.x * kGenTX;
+  const int a = u0 + 2 * lane, b = a + 1;
+  const bool has_a = a < W, has_b = b < W;
   const uint64_t *rowR = descR + (size_t)v * W * nw;
-  uint32_t best = 0xffffffffu;  // lane p < kGenTX: best key of pixel u0 + p
-  for (int dc0 = 0; dc0 < dmax; dc0 += 64) {
-    const int r_lo = u0 - dc0 - 63;
-    __syncthreads();
-    for (int i = lane; i < kGenWin * nw; i += 64) {
-      const int rel = i / nw, j = i - rel * nw;
-      const int r = r_lo + rel;
-      gwin[j * kGenWin + rel] = (r >= 0 && r < W) ? rowR[(size_t)r * nw + j] : 0;
-    }
-    __syncthreads();
-    const int d = dc0 + lane;
-    for (int p = 0; p < kGenTX; ++p) {
-      const int u = u0 + p;
-      if (u >= W) break;
-      const uint64_t *bl = descL + ((size_t)v * W + u) * nw;
-      const uint64_t *m = maskL ? maskL + ((size_t)v * W + u) * nw : nullptr;
-      const int rel = p + 63 - lane;  // right pixel u - d
-      uint32_t c = 0;
-      for (int j = 0; j < nw; ++j) {
-        uint64_t x = bl[j] ^ gwin[j * kGenWin + rel];
-        if (m) x &= m[j];
-        c += __popcll(x);
-      }
-      const bool valid = d < dmax && u - d >= 0;
-      uint32_t key = valid ? ((c << 16) | (uint32_t)d) : 0xffffffffu;
-      if (cost && d < dmax) cost[((size_t)d * H + v) * W + u] = (int16_t)(valid ? c : kInvalidCost);
+  const uint64_t *la = descL + ((size_t)v * W + (has_a ? a : 0)) * nw;
+  const uint64_t *lb = descL + ((size_t)v * W + (has_b ? b : 0)) * nw;
+  const uint64_t *qa = MASK ? maskL + ((size_t)v * W + (has_a ? a : 0)) * nw : nullptr;
+  const uint64_t *qb = MASK ? maskL + ((size_t)v * W + (has_b ? b : 0)) * nw : nullptr;
+  uint32_t best_a = 0xffffffffu, best_b = 0xffffffffu;
+
+  for (int dc0 = 0; dc0 < dmax; dc0 += kChunkD) {
+    const int nd = min(kChunkD, dmax - dc0);
+    const int r_lo = u0 - (dc0 + kChunkD) + 1;  // right pixel of relative index 0
+    uint32_t ca[kChunkD], cb[kChunkD];
 #pragma unroll
-      for (int s = 32; s >= 1; s >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, s));
-      if (lane == p) best = min(best, key);
+    for (int i = 0; i < kChunkD; ++i) ca[i] = cb[i] = 0;
+    for (int j0 = 0; j0 < nw; j0 += kChunkWords) {
+      __syncthreads();  // the previous chunk's window is consumed
+      for (int i = lane; i < kChunkP * kChunkWords; i += 64) {
+        const int rel = i / kChunkWords, w = i - rel * kChunkWords;
+        const int r = r_lo + rel, j = j0 + w;
+        const uint64_t x = (r >= 0 && r < W && j < nw) ? rowR[(size_t)r * nw + j] : 0;
+        cwin[(w * 2 + (rel & 1)) * kChunkHP + (rel >> 1)] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < kChunkWords; ++w) {
+        const int j = j0 + w;
+        const bool in = j < nw;
+        const uint64_t bla = (has_a && in) ? la[j] : 0, blb = (has_b && in) ? lb[j] : 0;
+        const uint64_t ma = (MASK && has_a && in) ? qa[j] : 0;
+        const uint64_t mb = (MASK && has_b && in) ? qb[j] : 0;
+        const uint64_t *ww = cwin + w * 2 * kChunkHP;
+        // relative index of right pixel a - d is 2 lane + (dc0 + kChunkD - 1 - d)
+        {
+          const int e = kChunkD - 1 + 1;  // b - dc0 = a - (dc0 - 1)
+          const int rel = 2 * lane + e;
+          const uint64_t br = ww[(rel & 1) * kChunkHP + (rel >> 1)];
+          cb[0] = masked_cost1(blb, mb, br, MASK, cb[0]);
+        }
+#pragma unroll
+        for (int i = 0; i < kChunkD; ++i) {
+          const int rel = 2 * lane + (kChunkD - 1 - i);
+          const uint64_t br = ww[(rel & 1) * kChunkHP + (rel >> 1)];
+          ca[i] = masked_cost1(bla, ma, br, MASK, ca[i]);
+          if (i + 1 < kChunkD) cb[i + 1] = masked_cost1(blb, mb, br, MASK, cb[i + 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kChunkD; ++i) {
+      if (i < nd) {
+        const int d = dc0 + i;
+        const bool va = a - d >= 0, vb = b - d >= 0;
+        if (va) best_a = min(best_a, (ca[i] << 16) | (uint32_t)d);
+        if (vb) best_b = min(best_b, (cb[i] << 16) | (uint32_t)d);
+        if (VOL) {
+          int16_t *plane = cost + ((size_t)d * H + v) * W;
+          const uint32_t sa = va ? ca[i] : (uint32_t)kInvalidCost;
+          const uint32_t sb = vb ? cb[i] : (uint32_t)kInvalidCost;
+          if (has_b && ((((size_t)d * H + v) * W) & 1) == 0) {
+            *reinterpret_cast<uint32_t *>(plane + a) = sa | (sb << 16);
+          } else {
+            if (has_a) plane[a] = (int16_t)sa;
+            if (has_b) plane[b] = (int16_t)sb;
+          }
+        }
+      }
     }
   }
-  if (lane < kGenTX && u0 + lane < W) disp[(size_t)v * W + u0 + lane] = (int32_t)(best & 0xffffu);
+  if (has_a) disp[(size_t)v * W + a] = (int32_t)(best_a & 0xffffu);
+  if (has_b) disp[(size_t)v * W + b] = (int32_t)(best_b & 0xffffu);
 }
 
 // ===========================================================================
@@ -1233,10 +1295,19 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const u
     case 16: return launch_cost_fast<16>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
     default: break;
   }
-  dim3 grid((W + kGenTX - 1) / kGenTX, H);
-  const size_t lds = (size_t)nw * kGenWin * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_cost_wta_generic, grid, dim3(64), lds, s, descL, maskL, descR, W, H, nw,
-                     dmax, disp, cost);
+  const int tiles = (W + kCostTX - 1) / kCostTX;
+  dim3 grid(kXcds * tiles * ((H + kXcds - 1) / kXcds));
+#define BSM_LAUNCH_CHUNKED(M, V)                                                             \
+  hipLaunchKernelGGL((k_cost_wta_chunked<M, V>), grid, dim3(64), kChunkLds, s, descL, maskL, \
+                     descR, W, H, nw, dmax, disp, cost)
+  if (maskL) {
+    if (cost) BSM_LAUNCH_CHUNKED(true, true);
+    else BSM_LAUNCH_CHUNKED(true, false);
+  } else {
+    if (cost) BSM_LAUNCH_CHUNKED(false, true);
+    else BSM_LAUNCH_CHUNKED(false, false);
+  }
+#undef BSM_LAUNCH_CHUNKED
   return hipGetLastError();
 }
 

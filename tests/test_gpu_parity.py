@@ -134,9 +134,13 @@ COST_CASES = [
     (450, 4, 16, 60, True, True),
     (129, 3, 2, 100, False, False),
     (260, 5, 8, 200, True, True),
-    (96, 4, 3, 40, True, True),     # generic kernel (nw not a power of two)
-    (150, 3, 24, 70, False, True),  # generic kernel
-    (70, 2, 64, 33, True, True),    # generic kernel, n = 4096
+    (96, 4, 3, 40, True, True),     # word-chunked kernel (nw not a power of two)
+    (150, 3, 24, 70, False, True),  # word-chunked kernel
+    (70, 2, 64, 33, True, True),    # word-chunked kernel, n = 4096
+    (301, 3, 32, 300, True, True),  # several disparity chunks, ragged tile
+    (1, 2, 5, 1, True, True),       # one pixel, partial word chunk
+    (259, 2, 64, 97, False, False), # n = 4096, Eq. 4
+    (200, 3, 9, 64, True, False),   # two full disparity chunks
 ]
 
 
