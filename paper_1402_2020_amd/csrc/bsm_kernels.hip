@@ -820,7 +820,7 @@ __global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict
 constexpr int kChunkD = 32, kChunkWords = 4;
 constexpr int kChunkP = kCostTX - 1 + kChunkD;      // window pixels
 constexpr int kChunkHP = (kChunkP + 1) / 2 + 1;     // pixels per parity half
-constexpr size_t kChunkLds = (size_t)kChunkWords * 2 * kChunkHP * sizeof(uint64_t);
+constexpr size_t kChunkLds = 2 * (size_t)(kChunkWords / 2) * 2 * kChunkHP * 2 * sizeof(uint64_t);
 
 __device__ __forceinline__ uint32_t masked_cost1(uint64_t bl, uint64_t m, uint64_t br, bool use_mask,
                                                  uint32_t c) {
@@ -835,6 +835,77 @@ __device__ __forceinline__ uint32_t masked_cost1(uint64_t bl, uint64_t m, uint64
   return bcnt_acc(hi, bcnt_acc(lo, c));
 }
 
+// Window elements a lane stages per chunk: kChunkP pixels x kChunkWords,
+// taken as 16-byte pairs of words.
+constexpr int kChunkPairs = kChunkWords / 2;
+constexpr int kChunkStage = (kChunkP * kChunkPairs + 63) / 64;
+
+// The steps of a tile are (disparity chunk, word chunk) pairs in order; the
+// global loads of step s + 1 (right window into registers, then LDS; the
+// lane's left words and mask words) are issued before step s computes, so
+// their latency hides behind a step's arithmetic.  Words travel in 16-byte
+// pairs when nw is even (every pixel's words are then 16-byte aligned).
+struct ChunkLoads {
+  uint64_t win[kChunkStage][2];
+  uint64_t la[kChunkWords], lb[kChunkWords], ma[kChunkWords], mb[kChunkWords];
+};
+
+// Words j, j + 1 of a pixel's string p (zeros past nw or for a missing
+// pixel); `pairs` = nw is even.
+__device__ __forceinline__ void load_word_pair(const uint64_t *p, int j, int nw, bool present,
+                                               bool pairs, uint64_t &x, uint64_t &y) {
+  x = y = 0;
+  if (!present || j >= nw) return;
+  if (pairs) {
+    const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(p + j);
+    x = t.x;
+    y = t.y;
+  } else {
+    x = p[j];
+    if (j + 1 < nw) y = p[j + 1];
+  }
+}
+
+template <bool MASK>
+__device__ __forceinline__ void chunk_load(ChunkLoads &L, const uint64_t *__restrict__ rowR,
+                                           const uint64_t *la, const uint64_t *lb,
+                                           const uint64_t *qa, const uint64_t *qb, bool has_a,
+                                           bool has_b, int W, int nw, int r_lo, int j0,
+                                           int lane) {
+  const bool pairs = (nw & 1) == 0;
+#pragma unroll
+  for (int k = 0; k < kChunkStage; ++k) {
+    const int i = lane + 64 * k;
+    const int rel = i / kChunkPairs, h = i - rel * kChunkPairs;
+    const int r = r_lo + rel;
+    load_word_pair(rowR + (size_t)(r >= 0 ? r : 0) * nw, j0 + 2 * h, nw,
+                   i < kChunkP * kChunkPairs && r >= 0 && r < W, pairs, L.win[k][0], L.win[k][1]);
+  }
+#pragma unroll
+  for (int h = 0; h < kChunkPairs; ++h) {
+    const int j = j0 + 2 * h;
+    load_word_pair(la, j, nw, has_a, pairs, L.la[2 * h], L.la[2 * h + 1]);
+    load_word_pair(lb, j, nw, has_b, pairs, L.lb[2 * h], L.lb[2 * h + 1]);
+    if (MASK) {
+      load_word_pair(qa, j, nw, has_a, pairs, L.ma[2 * h], L.ma[2 * h + 1]);
+      load_word_pair(qb, j, nw, has_b, pairs, L.mb[2 * h], L.mb[2 * h + 1]);
+    } else {
+      L.ma[2 * h] = L.ma[2 * h + 1] = L.mb[2 * h] = L.mb[2 * h + 1] = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ void chunk_store_window(const ChunkLoads &L, ulonglong2 *buf, int lane) {
+#pragma unroll
+  for (int k = 0; k < kChunkStage; ++k) {
+    const int i = lane + 64 * k;
+    if (i < kChunkP * kChunkPairs) {
+      const int rel = i / kChunkPairs, h = i - rel * kChunkPairs;
+      buf[(h * 2 + (rel & 1)) * kChunkHP + (rel >> 1)] = make_ulonglong2(L.win[k][0], L.win[k][1]);
+    }
+  }
+}
+
 template <bool MASK, bool VOL>
 __global__ __launch_bounds__(64) void k_cost_wta_chunked(const uint64_t *__restrict__ descL,
                                                          const uint64_t *__restrict__ maskL,
@@ -842,7 +913,8 @@ __global__ __launch_bounds__(64) void k_cost_wta_chunked(const uint64_t *__restr
                                                          int H, int nw, int dmax,
                                                          int32_t *__restrict__ disp,
                                                          int16_t *__restrict__ cost) {
-  extern __shared__ uint64_t cwin[];  // [kChunkWords][2][kChunkHP]
+  extern __shared__ ulonglong2 cwin[];  // two buffers of [kChunkPairs][2][kChunkHP]
+  constexpr int kBuf = kChunkPairs * 2 * kChunkHP;
   const int tiles = (W + kCostTX - 1) / kCostTX;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int v = xcd + kXcds * (slot / tiles);
@@ -856,66 +928,82 @@ __global__ __launch_bounds__(64) void k_cost_wta_chunked(const uint64_t *__restr
   const uint64_t *lb = descL + ((size_t)v * W + (has_b ? b : 0)) * nw;
   const uint64_t *qa = MASK ? maskL + ((size_t)v * W + (has_a ? a : 0)) * nw : nullptr;
   const uint64_t *qb = MASK ? maskL + ((size_t)v * W + (has_b ? b : 0)) * nw : nullptr;
+  const int nwc = (nw + kChunkWords - 1) / kChunkWords;   // word chunks
+  const int ndc = (dmax + kChunkD - 1) / kChunkD;         // disparity chunks
+  const int steps = nwc * ndc;
   uint32_t best_a = 0xffffffffu, best_b = 0xffffffffu;
+  uint32_t ca[kChunkD], cb[kChunkD];
 
-  for (int dc0 = 0; dc0 < dmax; dc0 += kChunkD) {
-    const int nd = min(kChunkD, dmax - dc0);
-    const int r_lo = u0 - (dc0 + kChunkD) + 1;  // right pixel of relative index 0
-    uint32_t ca[kChunkD], cb[kChunkD];
+  ChunkLoads cur, next;
+  // right pixel of relative index 0 for disparity chunk dc: u0 - dc*kChunkD - kChunkD + 1
+  chunk_load<MASK>(cur, rowR, la, lb, qa, qb, has_a, has_b, W, nw, u0 - kChunkD + 1, 0, lane);
+  chunk_store_window(cur, cwin, lane);
+  __syncthreads();
+
+  for (int s = 0; s < steps; ++s) {
+    const int dci = s / nwc, wci = s - dci * nwc;
+    const int dc0 = dci * kChunkD;
+    if (wci == 0) {
 #pragma unroll
-    for (int i = 0; i < kChunkD; ++i) ca[i] = cb[i] = 0;
-    for (int j0 = 0; j0 < nw; j0 += kChunkWords) {
-      __syncthreads();  // the previous chunk's window is consumed
-      for (int i = lane; i < kChunkP * kChunkWords; i += 64) {
-        const int rel = i / kChunkWords, w = i - rel * kChunkWords;
-        const int r = r_lo + rel, j = j0 + w;
-        const uint64_t x = (r >= 0 && r < W && j < nw) ? rowR[(size_t)r * nw + j] : 0;
-        cwin[(w * 2 + (rel & 1)) * kChunkHP + (rel >> 1)] = x;
+      for (int i = 0; i < kChunkD; ++i) ca[i] = cb[i] = 0;
+    }
+    if (s + 1 < steps) {  // prefetch step s + 1
+      const int dn = (s + 1) / nwc, wn = (s + 1) - dn * nwc;
+      chunk_load<MASK>(next, rowR, la, lb, qa, qb, has_a, has_b, W, nw,
+                       u0 - dn * kChunkD - kChunkD + 1, wn * kChunkWords, lane);
+    }
+    const ulonglong2 *buf = cwin + (s & 1) * kBuf;
+#pragma unroll
+    for (int h = 0; h < kChunkPairs; ++h) {
+      const ulonglong2 *ww = buf + h * 2 * kChunkHP;
+      const uint64_t la0 = cur.la[2 * h], la1 = cur.la[2 * h + 1];
+      const uint64_t lb0 = cur.lb[2 * h], lb1 = cur.lb[2 * h + 1];
+      const uint64_t ma0 = cur.ma[2 * h], ma1 = cur.ma[2 * h + 1];
+      const uint64_t mb0 = cur.mb[2 * h], mb1 = cur.mb[2 * h + 1];
+      {
+        const int rel = 2 * lane + kChunkD;  // right pixel b - dc0
+        const ulonglong2 br = ww[(rel & 1) * kChunkHP + (rel >> 1)];
+        cb[0] = masked_cost1(lb1, mb1, br.y, MASK, masked_cost1(lb0, mb0, br.x, MASK, cb[0]));
       }
-      __syncthreads();
 #pragma unroll
-      for (int w = 0; w < kChunkWords; ++w) {
-        const int j = j0 + w;
-        const bool in = j < nw;
-        const uint64_t bla = (has_a && in) ? la[j] : 0, blb = (has_b && in) ? lb[j] : 0;
-        const uint64_t ma = (MASK && has_a && in) ? qa[j] : 0;
-        const uint64_t mb = (MASK && has_b && in) ? qb[j] : 0;
-        const uint64_t *ww = cwin + w * 2 * kChunkHP;
-        // relative index of right pixel a - d is 2 lane + (dc0 + kChunkD - 1 - d)
-        {
-          const int e = kChunkD - 1 + 1;  // b - dc0 = a - (dc0 - 1)
-          const int rel = 2 * lane + e;
-          const uint64_t br = ww[(rel & 1) * kChunkHP + (rel >> 1)];
-          cb[0] = masked_cost1(blb, mb, br, MASK, cb[0]);
-        }
-#pragma unroll
-        for (int i = 0; i < kChunkD; ++i) {
-          const int rel = 2 * lane + (kChunkD - 1 - i);
-          const uint64_t br = ww[(rel & 1) * kChunkHP + (rel >> 1)];
-          ca[i] = masked_cost1(bla, ma, br, MASK, ca[i]);
-          if (i + 1 < kChunkD) cb[i + 1] = masked_cost1(blb, mb, br, MASK, cb[i + 1]);
-        }
+      for (int i = 0; i < kChunkD; ++i) {
+        const int rel = 2 * lane + (kChunkD - 1 - i);  // right pixel a - (dc0 + i)
+        const ulonglong2 br = ww[(rel & 1) * kChunkHP + (rel >> 1)];
+        ca[i] = masked_cost1(la1, ma1, br.y, MASK, masked_cost1(la0, ma0, br.x, MASK, ca[i]));
+        if (i + 1 < kChunkD)
+          cb[i + 1] =
+              masked_cost1(lb1, mb1, br.y, MASK, masked_cost1(lb0, mb0, br.x, MASK, cb[i + 1]));
       }
     }
+    if (wci == nwc - 1) {  // the disparity chunk is complete
+      const int nd = min(kChunkD, dmax - dc0);
 #pragma unroll
-    for (int i = 0; i < kChunkD; ++i) {
-      if (i < nd) {
-        const int d = dc0 + i;
-        const bool va = a - d >= 0, vb = b - d >= 0;
-        if (va) best_a = min(best_a, (ca[i] << 16) | (uint32_t)d);
-        if (vb) best_b = min(best_b, (cb[i] << 16) | (uint32_t)d);
-        if (VOL) {
-          int16_t *plane = cost + ((size_t)d * H + v) * W;
-          const uint32_t sa = va ? ca[i] : (uint32_t)kInvalidCost;
-          const uint32_t sb = vb ? cb[i] : (uint32_t)kInvalidCost;
-          if (has_b && ((((size_t)d * H + v) * W) & 1) == 0) {
-            *reinterpret_cast<uint32_t *>(plane + a) = sa | (sb << 16);
-          } else {
-            if (has_a) plane[a] = (int16_t)sa;
-            if (has_b) plane[b] = (int16_t)sb;
+      for (int i = 0; i < kChunkD; ++i) {
+        if (i < nd) {
+          const int d = dc0 + i;
+          const bool va = a - d >= 0, vb = b - d >= 0;
+          if (va) best_a = min(best_a, (ca[i] << 16) | (uint32_t)d);
+          if (vb) best_b = min(best_b, (cb[i] << 16) | (uint32_t)d);
+          if (VOL) {
+            int16_t *plane = cost + ((size_t)d * H + v) * W;
+            const uint32_t sa = va ? ca[i] : (uint32_t)kInvalidCost;
+            const uint32_t sb = vb ? cb[i] : (uint32_t)kInvalidCost;
+            if (has_b && ((((size_t)d * H + v) * W) & 1) == 0) {
+              *reinterpret_cast<uint32_t *>(plane + a) = sa | (sb << 16);
+            } else {
+              if (has_a) plane[a] = (int16_t)sa;
+              if (has_b) plane[b] = (int16_t)sb;
+            }
           }
         }
       }
+    }
+    if (s + 1 < steps) {
+      // the other buffer was last read in step s - 1, which every lane of
+      // this one-wave workgroup has finished
+      chunk_store_window(next, cwin + ((s + 1) & 1) * kBuf, lane);
+      cur = next;
+      __syncthreads();
     }
   }
   if (has_a) disp[(size_t)v * W + a] = (int32_t)(best_a & 0xffffu);
