@@ -35,7 +35,20 @@ WORKLOADS = {
     4: "serving: Poisson arrivals of the 64 uneven pairs, n 1024, S 31, 32 GiB admission cap",
     5: "descriptor-length sweep: 1400x1100 slanted planes + radiometric change, dmax 256, S 31, "
        "n 64..4096",
+    6: "radiometric sweep: 450x375 slanted planes, dmax 60, n 1024, S 31, right view under gain / "
+       "gamma / offset changes, BSM (Eq. 8) vs plain BRIEF (Eq. 4)",
 }
+
+RADIOMETRIC = [  # name, gain, gamma, per-channel offset
+    ("none", 1.0, 1.0, (0, 0, 0)),
+    ("gain 0.5", 0.5, 1.0, (0, 0, 0)),
+    ("gain 2.0", 2.0, 1.0, (0, 0, 0)),
+    ("gamma 0.7", 1.0, 0.7, (0, 0, 0)),
+    ("gamma 1.4", 1.0, 1.4, (0, 0, 0)),
+    ("offset +20", 1.0, 1.0, (20, 20, 20)),
+    ("offset -20/+10/+20", 1.0, 1.0, (-20, 10, 20)),
+    ("gain 1.6 gamma 0.8 offset 15/-10/5", 1.6, 0.8, (15, -10, 5)),
+]
 
 
 def bench_batch(args):
@@ -336,6 +349,77 @@ def bench_nsweep(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_radiometric(args):
+    """Quality under radiometric change (the idea of the paper's Section 4.2
+    on synthetic ground truth): bad-pixel rate (|d - gt| > 1 px over
+    non-occluded left pixels) of BSM (mask, Eq. 8) and plain BRIEF (Eq. 4)
+    as the right view's exposure, gamma and offsets change; plus the share
+    of pixels the left/right check keeps and the bad rate among them."""
+    import numpy as np
+    import torch
+
+    from paper_1402_2020_amd import _bsm, synth
+    dmax, n, S = 60, 1024, 31
+    sigma = 4.0 * S / 26
+    pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
+    bsm = _bsm.Context(n, S, sigma, pattern=pat, use_mask=True, device=0)
+    brief = _bsm.Context(n, S, sigma, pattern=pat, use_mask=False, device=0)
+    dev = torch.device("cuda:0")
+    rows = []
+    t0 = time.perf_counter()
+    # the 450x375 scene as generated, and the same geometry with a distinct
+    # colour per surface
+    for scene_name, scene in (("textured", synth.config_scene(1)),
+                              ("tinted", synth.slanted_scene(14022021, 450, 375, 60, tinted=True))):
+        H, W = scene.left.shape[:2]
+        L = torch.from_numpy(scene.left).to(dev)
+        valid = synth.non_occluded(scene)
+        edge = valid & synth.near_discontinuity(scene)
+        gt = scene.gt
+        for name, gain, gamma, off in RADIOMETRIC:
+            Rn = synth.radiometric(scene.right, gain, gamma, off)
+            R = torch.from_numpy(Rn).to(dev)
+            row = {"scene": scene_name, "change": name}
+            for tag, ctx in (("bsm", bsm), ("brief", brief)):
+                dl, _ = ctx.match(L, R, dmax)
+                bad = np.abs(dl.cpu().numpy() - gt) > 1.0
+                row[f"{tag}_bad_pct"] = round(100.0 * float(bad[valid].mean()), 3)
+                row[f"{tag}_bad_near_edges_pct"] = round(100.0 * float(bad[edge].mean()), 3)
+            dl, _ = bsm.match(L, R, dmax)
+            dr, _ = bsm.match_right(L, R, dmax)
+            chk = bsm.lr_check(dl, dr, tol=1).cpu().numpy()
+            kept = (chk >= 0) & valid
+            row["bsm_lr_kept_pct"] = round(100.0 * float(kept.sum() / valid.sum()), 3)
+            row["bsm_lr_kept_bad_pct"] = round(
+                100.0 * float((np.abs(chk - gt) > 1.0)[kept].mean()) if kept.any() else 0.0, 3)
+            rows.append(row)
+            print(json.dumps({"progress": "radiometric", **row}), flush=True)
+    elapsed = time.perf_counter() - t0
+    last = rows[-1]
+    out = {
+        "metric": "bad pixel % (|d - gt| > 1 px, non-occluded)",
+        "value": last["bsm_bad_pct"],
+        "unit": "%",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": 0,
+        "ms_per_step": 1e3 * elapsed / len(rows),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded scene generator with ground truth; stand-in for the paper's "
+                "radiometric datasets)",
+        "config": {"workload": WORKLOADS[6], "W": 450, "H": 375, "dmax": dmax, "n_bits": n,
+                   "window": S},
+        "sweep": rows,
+        "roofline": None,
+    }
+    bsm.close()
+    brief.close()
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources_hash():
     h = hashlib.sha256()
     for name in ("bsm_kernels.hip",):
@@ -423,6 +507,8 @@ def main():
         return bench_serve(args)
     if cfg == 5:
         return bench_nsweep(args)
+    if cfg == 6:
+        return bench_radiometric(args)
     p = synth.CONFIG_PARAMS[cfg]
     scene = synth.config_scene(cfg)
     H, W = scene.left.shape[:2]

@@ -124,7 +124,7 @@ def _bilinear(t, x, y):
 
 
 def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
-                  noise=3.0, max_grad=0.2, radiometric=False):
+                  noise=3.0, max_grad=0.2, radiometric=False, tinted=False):
     """Slanted-plane scene: a background plane and n_regions planar patches.
 
     Patch k covers a rectangle or an ellipse (10-40 % of W and H) in left
@@ -133,7 +133,9 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
     win in both views, which leaves occlusion bands at discontinuities.  Each
     surface has its own texture, sampled bilinearly.  Both views get Gaussian
     noise; optionally the right view gets a global gain, gamma and
-    per-channel offset.
+    per-channel offset.  With tinted=True every surface's texture gets its
+    own colour offset (objects of distinct colours, as in natural scenes);
+    the default draws exactly the random numbers it always did.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     Wc = W + dmax + 2
@@ -164,6 +166,9 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
             c = rng.uniform(min(lo_d + span, hi_d), max(hi_d - span, lo_d + span))
         planes.append(dict(kind=kind, uc=uc, vc=vc, rw=rw, rh=rh, a=a, b=b, c=c))
     tex = [texture(rng, H, Wc) for _ in planes]
+    if tinted:
+        tint_rng = np.random.Generator(np.random.PCG64(seed + 0x7E57))
+        tex = [t + tint_rng.uniform(-60.0, 60.0, 3) for t in tex]
 
     def disp(p, u, v):
         d = p["a"] * (u - p["uc"]) + p["b"] * (v - p["vc"]) + p["c"]
@@ -181,6 +186,7 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
     left = np.zeros((H, W, 3))
     right = np.zeros((H, W, 3))
     gt = np.zeros((H, W), np.float32)
+    gt_right = np.full((H, W), -1.0, np.float32)  # right-view disparity, -1: no surface
     u = np.arange(W, dtype=np.float64)
     for v in range(H):
         zl = np.full(W, -1.0)
@@ -201,13 +207,14 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
             if selr.any():
                 right[v, selr] = _bilinear(t, ul[selr], v)
                 zr[selr] = dl[selr]
+        gt_right[v] = zr
         # right pixels no surface reaches (background clamping at edges)
         hole = zr < 0
         if hole.any():
             right[v, hole] = _bilinear(tex[0], u[hole] + planes[0]["c"], v)
     left = add_noise(rng, left, noise)
     right = add_noise(rng, right, noise)
-    meta = {"kind": "slanted", "planes": planes}
+    meta = {"kind": "slanted", "planes": planes, "gt_right": gt_right}
     if radiometric:
         g = rng.uniform(0.5, 2.0)
         gamma = rng.uniform(0.7, 1.4)
@@ -219,6 +226,37 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
 
 
 # --- the workloads -------------------------------------------------------
+
+def radiometric(img: np.ndarray, gain=1.0, gamma=1.0, offset=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """A global radiometric change of an 8-bit RGB view (exposure gain, gamma
+    and per-channel offset, clamped), the kind of change the paper's
+    radiometric experiments apply to one view."""
+    x = img.astype(np.float64)
+    y = 255.0 * np.minimum(1.0, gain * x / 255.0) ** gamma + np.asarray(offset, np.float64)
+    return to_u8(y)
+
+
+def near_discontinuity(scene: Scene, band=5, jump=1.0) -> np.ndarray:
+    """Left pixels within `band` columns or rows of a ground-truth depth jump
+    larger than `jump` px (where fattening errors appear)."""
+    from scipy.ndimage import binary_dilation
+    gt = scene.gt
+    edge = np.zeros(gt.shape, bool)
+    edge[:, 1:] |= np.abs(np.diff(gt, axis=1)) > jump
+    edge[1:, :] |= np.abs(np.diff(gt, axis=0)) > jump
+    return binary_dilation(edge, iterations=band)
+
+
+def non_occluded(scene: Scene, tol=1.0) -> np.ndarray:
+    """Left pixels whose ground-truth partner in the right view shows the
+    same surface (the right view's ground truth agrees within tol)."""
+    gt, gtr = scene.gt, scene.meta["gt_right"]
+    H, W = gt.shape
+    ur = np.rint(np.arange(W)[None, :] - gt).astype(np.int64)
+    inside = (ur >= 0) & (ur < W)
+    partner = np.take_along_axis(gtr, np.clip(ur, 0, W - 1), axis=1)
+    return inside & (partner >= 0) & (np.abs(partner - gt) <= tol)
+
 
 def config_scene(cfg: int) -> Scene:
     """The single-pair workloads: 0 = 128x96 rectangles (dmax 16),
