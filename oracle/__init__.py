@@ -24,6 +24,7 @@ from .oracle import (  # noqa: F401
     set_threads,
     get_threads,
     splitmix64,
+    vote_refine,
     weights,
     wta,
 )

@@ -544,3 +544,72 @@ int oracle_lr_check(const int32_t *dL, const int32_t *dR, int W, int H,
         }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Voting refinement, Eq. 9-10 (the second part of Section 3's refinement   */
+/* step).  Readings: the voters of x are the valid pixels of the window of  */
+/* radius `radius` around x that lie inside the image; c is the Euclidean   */
+/* distance of the Lab8 colours (the colour space of the mask); e is the    */
+/* Euclidean distance of the pixel positions; argmax ties take the lowest  */
+/* d; a pixel without voters keeps the fallback disparity.                 */
+/* ------------------------------------------------------------------------ */
+
+int oracle_vote_refine(const uint8_t *rgb, int W, int H, int stride,
+                       const int32_t *checked, const int32_t *fallback,
+                       int radius, int dmax, double lambda_c, double lambda_e,
+                       int32_t *out, double *W_out)
+{
+    if (W < 1 || H < 1 || stride < 3 * W || !rgb || !checked || !fallback || !out ||
+        radius < 0 || dmax < 1 || !(lambda_c > 0) || !(lambda_e > 0))
+        return -1;
+    size_t npx = (size_t)W * H;
+    uint8_t *lab = (uint8_t *)malloc(npx * 3);
+    oracle_lab8(rgb, W, H, stride, lab);
+    if (W_out)
+        memset(W_out, 0, npx * dmax * sizeof(double));
+#pragma omp parallel for schedule(dynamic) num_threads(g_threads)
+    for (int v = 0; v < H; v++) {
+        double *acc = (double *)malloc(sizeof(double) * dmax);
+        for (int u = 0; u < W; u++) {
+            size_t x = (size_t)v * W + u;
+            if (checked[x] >= 0) {
+                out[x] = checked[x];
+                continue;
+            }
+            for (int d = 0; d < dmax; d++)
+                acc[d] = 0.0;
+            int voters = 0;
+            const uint8_t *cx = lab + 3 * x;
+            for (int dy = -radius; dy <= radius; dy++)
+                for (int dx = -radius; dx <= radius; dx++) {
+                    int pu = u + dx, pv = v + dy;
+                    if (pu < 0 || pu >= W || pv < 0 || pv >= H)
+                        continue;
+                    size_t p = (size_t)pv * W + pu;
+                    int d = checked[p];
+                    if (d < 0 || d >= dmax)
+                        continue;
+                    const uint8_t *cp = lab + 3 * p;
+                    double dl = (double)cx[0] - cp[0], da = (double)cx[1] - cp[1],
+                           db = (double)cx[2] - cp[2];
+                    double c = sqrt(dl * dl + da * da + db * db);
+                    double e = sqrt((double)dx * dx + (double)dy * dy);
+                    acc[d] += exp(-(c / lambda_c + e / lambda_e));
+                    voters++;
+                }
+            int best = fallback[x];
+            if (voters > 0) {
+                best = 0;
+                for (int d = 1; d < dmax; d++)
+                    if (acc[d] > acc[best])
+                        best = d;
+            }
+            out[x] = best;
+            if (W_out)
+                memcpy(W_out + x * dmax, acc, sizeof(double) * dmax);
+        }
+        free(acc);
+    }
+    free(lab);
+    return 0;
+}

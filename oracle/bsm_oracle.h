@@ -93,6 +93,21 @@ int oracle_match_right(const uint8_t *left, const uint8_t *right, int W, int H,
 int oracle_lr_check(const int32_t *dL, const int32_t *dR, int W, int H,
                     int tol, int32_t *out);
 
+/* Voting refinement (Section 3, Eq. 9-10) of the pixels the left/right
+ * check marked invalid (checked < 0): d_x = argmax over d in [0, dmax - 1]
+ * of W(x, d), the sum over valid pixels p (checked >= 0) with disparity d
+ * in the (2 radius + 1)^2 window around x, inside the image, of
+ * exp(-(c(x, p) / lambda_c + e(x, p) / lambda_e)); c = Euclidean distance of
+ * the 8-bit CIELAB colours, e = Euclidean distance of the positions.  Ties
+ * take the lowest d; an invalid pixel without any valid pixel in its window
+ * keeps fallback(x); valid pixels keep checked(x).  Double precision.
+ * W_out (optional, [H][W][dmax]) receives W(x, d) of invalid pixels (0
+ * elsewhere). */
+int oracle_vote_refine(const uint8_t *rgb, int W, int H, int stride,
+                       const int32_t *checked, const int32_t *fallback,
+                       int radius, int dmax, double lambda_c, double lambda_e,
+                       int32_t *out, double *W_out);
+
 #ifdef __cplusplus
 }
 #endif

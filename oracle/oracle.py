@@ -59,6 +59,9 @@ def load():
     lib.oracle_match_right.restype = ci
     lib.oracle_lr_check.argtypes = [i32p, i32p, ci, ci, ci, i32p]
     lib.oracle_lr_check.restype = ci
+    lib.oracle_vote_refine.argtypes = [u8p, ci, ci, ci, i32p, i32p, ci, ci, C.c_double, C.c_double,
+                                       i32p, C.POINTER(C.c_double)]
+    lib.oracle_vote_refine.restype = ci
     _lib = lib
     return lib
 
@@ -239,3 +242,21 @@ def lr_check(dL, dR, tol=1):
     _check(load().oracle_lr_check(_p(dL, C.c_int32), _p(dR, C.c_int32), W, H, int(tol),
                                   _p(out, C.c_int32)), "lr_check")
     return out
+
+
+def vote_refine(rgb, checked, fallback, dmax, radius, lambda_c=9.0, lambda_e=16.0,
+                want_votes=False):
+    """Voting refinement of Eq. 9-10: (refined disparity int32 [H][W],
+    W(x, d) float64 [H][W][dmax] of invalid pixels or None)."""
+    rgb, W, H, st = _img(rgb)
+    checked = np.ascontiguousarray(checked, np.int32)
+    fallback = np.ascontiguousarray(fallback, np.int32)
+    if checked.shape != (H, W) or fallback.shape != (H, W):
+        raise ValueError("checked and fallback must be [H][W]")
+    out = np.zeros((H, W), np.int32)
+    votes = np.zeros((H, W, dmax), np.float64) if want_votes else None
+    _check(load().oracle_vote_refine(_p(rgb, C.c_uint8), W, H, st, _p(checked, C.c_int32),
+                                     _p(fallback, C.c_int32), int(radius), int(dmax),
+                                     float(lambda_c), float(lambda_e), _p(out, C.c_int32),
+                                     _p(votes, C.c_double)), "vote_refine")
+    return out, votes
