@@ -199,6 +199,25 @@ bsm_status bsm_lr_check(bsm_ctx *ctx, const int32_t *disp_left,
                         const int32_t *disp_right, int32_t W, int32_t H,
                         int32_t tol, int32_t *out, void *hip_stream);
 
+/* Voting refinement (Section 3, Eq. 9-10) of the pixels a left/right check
+ * marked invalid (checked < 0): d(x) = the d in [0, dmax - 1] with the
+ * largest W(x, d), the sum over valid pixels p (checked >= 0) with
+ * disparity d in the (2 radius + 1)^2 window around x (inside the image) of
+ * exp(-(c(x, p) / lambda_c + e(x, p) / lambda_e)), c = Euclidean distance
+ * of the 8-bit CIELAB colours of the left view, e = Euclidean distance of
+ * the positions (the paper's lambda_c = 9, lambda_e = 16; it leaves the
+ * window and the colour space open, this library takes the matching window
+ * and CIELAB).  Ties take the lowest d; an invalid pixel without voters
+ * takes fallback(x) (e.g. the WTA disparity); valid pixels keep checked(x).
+ * Votes are summed in fp32.  left: device RGB; checked, fallback, out:
+ * device int32 [H][W], 4-byte aligned; out may be fallback but not
+ * checked.  1 <= dmax <= 4096, 0 <= radius <= 63.  Uses context scratch. */
+bsm_status bsm_vote_refine(bsm_ctx *ctx, const uint8_t *left, int32_t W,
+                           int32_t H, int32_t stride, const int32_t *checked,
+                           const int32_t *fallback, int32_t dmax,
+                           int32_t radius, float lambda_c, float lambda_e,
+                           int32_t *out, void *hip_stream);
+
 /* Many pairs of uneven size and dmax at once.  The tiles of all pairs go
  * into device work queues (largest pair first) served by one persistent
  * kernel per stage (colour, describe+mask, describe, cost+WTA); the four

@@ -19,7 +19,7 @@ INVALID_COST = 32767
 # Every symbol include/bsm.h declares.
 EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
            "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
-           "bsm_match_right", "bsm_lr_check",
+           "bsm_match_right", "bsm_lr_check", "bsm_vote_refine",
            "bsm_match_batch", "bsm_get_tuning", "bsm_set_tuning", "bsm_autotune",
            "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain", "bsm_serve_stats")
 
@@ -102,6 +102,8 @@ def load():
         "bsm_match": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
         "bsm_match_right": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
         "bsm_lr_check": ([vp, vp, vp, i32, i32, i32, vp, vp], st),
+        "bsm_vote_refine": ([vp, vp, i32, i32, i32, vp, vp, i32, i32, C.c_float, C.c_float, vp, vp],
+                            st),
         "bsm_match_batch": ([vp, C.POINTER(Pair), i32, vp], st),
         "bsm_get_tuning": ([vp, C.POINTER(Tuning)], st),
         "bsm_set_tuning": ([vp, C.POINTER(Tuning)], st),
@@ -196,6 +198,12 @@ def bsm_lr_check(ctx, disp_left, disp_right, W, H, tol, out, stream):
     return load().bsm_lr_check(ctx, disp_left, disp_right, W, H, tol, out, stream)
 
 
+def bsm_vote_refine(ctx, left, W, H, stride, checked, fallback, dmax, radius, lambda_c, lambda_e,
+                    out, stream):
+    return load().bsm_vote_refine(ctx, left, W, H, stride, checked, fallback, dmax, radius,
+                                  lambda_c, lambda_e, out, stream)
+
+
 def bsm_match_batch(ctx, pairs, stream):
     arr = (Pair * len(pairs))(*pairs)
     return load().bsm_match_batch(ctx, arr, len(pairs), stream)
@@ -266,6 +274,7 @@ class Context:
                  use_mask=True, device=0):
         self.n = n_bits
         self.nw = n_bits // 64
+        self.window = window
         self.device = device
         self.use_mask = bool(use_mask)
         self.h = bsm_create(n_bits, window, sigma, seed, pattern, mask_rank, use_mask, device)
@@ -369,6 +378,20 @@ class Context:
             out = torch.empty_like(disp_left)
         _check(bsm_lr_check(self.h, _ptr(disp_left), _ptr(disp_right), W, H, tol, _ptr(out),
                             _stream(stream)), "bsm_lr_check")
+        return out
+
+    def vote_refine(self, left, checked, fallback, dmax, radius=None, lambda_c=9.0, lambda_e=16.0,
+                    out=None, stream=None):
+        """Voting refinement of the pixels `checked` marks invalid (< 0);
+        radius defaults to half the matching window."""
+        import torch
+        left, W, H, st = self._img(left)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.int32, device=left.device)
+        r = self.window // 2 if radius is None else radius
+        _check(bsm_vote_refine(self.h, _ptr(left), W, H, st, _ptr(checked), _ptr(fallback), dmax,
+                               r, lambda_c, lambda_e, _ptr(out), _stream(stream)),
+               "bsm_vote_refine")
         return out
 
     def tuning(self):

@@ -659,4 +659,41 @@ bsm_status bsm_lr_check(bsm_ctx *ctx, const int32_t *disp_left, const int32_t *d
   return BSM_OK;
 }
 
+bsm_status bsm_vote_refine(bsm_ctx *ctx, const uint8_t *left, int32_t W, int32_t H,
+                           int32_t stride, const int32_t *checked, const int32_t *fallback,
+                           int32_t dmax, int32_t radius, float lambda_c, float lambda_e,
+                           int32_t *out, void *hip_stream) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_image(left, W, H, stride)) != BSM_OK) return st;
+  if (dmax < 1 || dmax > kMaxVoteDmax)
+    return fail(BSM_EINVAL, "dmax %d out of [1, %d]", dmax, kMaxVoteDmax);
+  if (radius < 0 || radius > kMaxWindow)
+    return fail(BSM_EINVAL, "radius %d out of [0, %d]", radius, kMaxWindow);
+  if (!(lambda_c > 0.0f) || !(lambda_e > 0.0f))
+    return fail(BSM_EINVAL, "lambda_c and lambda_e must be > 0");
+  if (!checked || !fallback || !out)
+    return fail(BSM_EINVAL, "checked, fallback and out must not be NULL");
+  if ((reinterpret_cast<uintptr_t>(checked) | reinterpret_cast<uintptr_t>(fallback) |
+       reinterpret_cast<uintptr_t>(out)) & 3u)
+    return fail(BSM_EINVAL, "disparity maps must be 4-byte aligned");
+  if (out == checked) return fail(BSM_EINVAL, "out must not alias checked");
+  DeviceGuard g(ctx->device);
+  if (g.err() != hipSuccess) return device_fail(ctx, g.err(), "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  void *buf = ctx->describe_scratch.acquire((size_t)W * H * 4, s, &e);
+  if (!buf) return device_fail(ctx, e, "refinement scratch");
+  uint32_t *packed = static_cast<uint32_t *>(buf);
+  if ((e = launch_color(left, W, H, stride, packed, 1, 0, ctx->dt, s)) != hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass (refinement)");
+  if ((e = launch_vote_refine(packed, checked, fallback, W, H, dmax, radius, lambda_c, lambda_e,
+                              out, s)) != hipSuccess)
+    return device_fail(ctx, e, "voting refinement");
+  if ((e = ctx->describe_scratch.release(s)) != hipSuccess)
+    return device_fail(ctx, e, "refinement scratch event");
+  return BSM_OK;
+}
+
 }  // extern "C"

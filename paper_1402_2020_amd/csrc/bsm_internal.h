@@ -112,6 +112,10 @@ hipError_t launch_reverse_rows(int32_t *data, int W, int rows, hipStream_t s);
 hipError_t launch_reverse_rows(int16_t *data, int W, int rows, hipStream_t s);
 hipError_t launch_lr_check(const int32_t *dL, const int32_t *dR, int W, int H, int tol,
                            int32_t *out, hipStream_t s);
+hipError_t launch_vote_refine(const uint32_t *packed, const int32_t *checked,
+                              const int32_t *fallback, int W, int H, int dmax, int radius,
+                              float lambda_c, float lambda_e, int32_t *out, hipStream_t s);
+constexpr int kMaxVoteDmax = 4096;  // LDS histogram of the voting kernel
 hipError_t launch_describe(const uint32_t *packed, int W, int H,
                            const DeviceTables &t, uint64_t *desc,
                            uint64_t *mask, hipStream_t s);

@@ -1011,6 +1011,82 @@ __global__ __launch_bounds__(64) void k_cost_wta_chunked(const uint64_t *__restr
 }
 
 // ===========================================================================
+// Voting refinement (Eq. 9-10) of the pixels the left/right check marked
+// invalid.  One wave per pixel: the lanes walk the (2 radius + 1)^2 window,
+// every valid pixel p adds its bilateral weight
+// exp(-(c / lambda_c + e / lambda_e)) (c: Euclidean distance of the Lab8
+// colours, e: of the positions) to the wave's histogram over d in LDS, then
+// the wave takes the largest vote, the lowest d among equal votes.  A pixel
+// without voters keeps its fallback disparity; valid pixels keep theirs.
+// Votes are summed in fp32 (the order of the LDS additions is the
+// hardware's).
+// ===========================================================================
+constexpr int kVoteWaves = 4;
+
+__global__ __launch_bounds__(64 * kVoteWaves) void k_vote_refine(
+    const uint32_t *__restrict__ packed, const int32_t *__restrict__ checked,
+    const int32_t *__restrict__ fallback, int W, int H, int dmax, int radius, float lambda_c,
+    float lambda_e, int32_t *__restrict__ out) {
+  extern __shared__ float votes[];  // [kVoteWaves][dmax]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long x = (long long)blockIdx.x * kVoteWaves + wave;
+  const bool live = x < (long long)W * H;
+  const int u = live ? (int)(x % W) : 0, v = live ? (int)(x / W) : 0;
+  const int own = live ? checked[x] : 0;
+  const bool refine = live && own < 0;  // wave-uniform
+  float *hist = votes + wave * dmax;
+  if (refine)
+    for (int d = lane; d < dmax; d += 64) hist[d] = 0.0f;
+  __syncthreads();
+  bool voted = false;
+  if (refine) {
+    const uint32_t cx = packed[x];
+    const int side = 2 * radius + 1;
+    for (int i = lane; i < side * side; i += 64) {
+      const int dy = i / side - radius, dx = i % side - radius;
+      const int pu = u + dx, pv = v + dy;
+      if (pu < 0 || pu >= W || pv < 0 || pv >= H) continue;
+      const size_t p = (size_t)pv * W + pu;
+      const int d = checked[p];
+      if (d < 0 || d >= dmax) continue;
+      const uint32_t cp = packed[p];
+      const float dl = (float)(int)(cx & 0xff) - (float)(int)(cp & 0xff);
+      const float da = (float)(int)((cx >> 8) & 0xff) - (float)(int)((cp >> 8) & 0xff);
+      const float db = (float)(int)((cx >> 16) & 0xff) - (float)(int)((cp >> 16) & 0xff);
+      const float c = sqrtf(dl * dl + da * da + db * db);
+      const float e = sqrtf((float)(dx * dx + dy * dy));
+      atomicAdd(&hist[d], expf(-(c / lambda_c + e / lambda_e)));
+      voted = true;
+    }
+  }
+  __syncthreads();
+  if (!refine) {
+    if (live && lane == 0) out[x] = own;
+    return;
+  }
+  float best = -1.0f;
+  int best_d = 0;
+  for (int d = lane; d < dmax; d += 64) {
+    const float w = hist[d];
+    if (w > best) {  // ascending d: keeps the lowest d among equal votes
+      best = w;
+      best_d = d;
+    }
+  }
+#pragma unroll
+  for (int sft = 32; sft >= 1; sft >>= 1) {
+    const float ow = __shfl_xor(best, sft);
+    const int od = __shfl_xor(best_d, sft);
+    if (ow > best || (ow == best && od < best_d)) {
+      best = ow;
+      best_d = od;
+    }
+  }
+  const bool any = __ballot(voted) != 0;
+  if (lane == 0) out[x] = any ? best_d : fallback[x];
+}
+
+// ===========================================================================
 // Persistent batch kernels.  Every stage kernel loops: a workgroup takes the
 // next tile index of its queue with one atomic add, finds the pair that owns
 // it (binary search over per-pair prefix sums; pairs are listed largest work
@@ -1342,6 +1418,17 @@ hipError_t launch_reverse_rows(int32_t *data, int W, int rows, hipStream_t s) {
 
 hipError_t launch_reverse_rows(int16_t *data, int W, int rows, hipStream_t s) {
   return launch_reverse_rows_t(data, W, rows, s);
+}
+
+hipError_t launch_vote_refine(const uint32_t *packed, const int32_t *checked,
+                              const int32_t *fallback, int W, int H, int dmax, int radius,
+                              float lambda_c, float lambda_e, int32_t *out, hipStream_t s) {
+  const long long px = (long long)W * H;
+  dim3 grid((unsigned)((px + kVoteWaves - 1) / kVoteWaves));
+  hipLaunchKernelGGL(k_vote_refine, grid, dim3(64 * kVoteWaves),
+                     (size_t)kVoteWaves * dmax * sizeof(float), s, packed, checked, fallback, W, H,
+                     dmax, radius, lambda_c, lambda_e, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_lr_check(const int32_t *dL, const int32_t *dR, int W, int H, int tol,
