@@ -1095,6 +1095,17 @@ __global__ __launch_bounds__(64 * kVoteWaves) void k_vote_refine(
 // previous stages completed; no workgroup ever waits for another.
 // ===========================================================================
 
+// A wave-uniform value pinned to scalar registers.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename T>
+__device__ __forceinline__ T *uniform(T *p) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
+  const uint32_t hi =
+      static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x >> 32)));
+  return reinterpret_cast<T *>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // Largest i in [0, npairs) with start[i] <= t (start[npairs] > t).
 __device__ __forceinline__ int owner(const int *start, int npairs, int t) {
   int lo = 0, hi = npairs;
@@ -1142,7 +1153,7 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
 }
 
 template <int NW, int TW>
-__global__ __launch_bounds__(kDescThreads) void k_batch_describe_mask(
+__global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe_mask(
     const BatchWork *__restrict__ bw, DescribeConsts c) {
   extern __shared__ uint32_t tile[];
   __shared__ int slot;
@@ -1153,10 +1164,11 @@ __global__ __launch_bounds__(kDescThreads) void k_batch_describe_mask(
     if (t >= total) break;
     const int i = owner(start, bw->npairs, t);
     const BatchPair &p = bw->pairs[bw->order[i]];
-    const int tx = (p.W + TW - 1) / TW;
+    const int W = uniform(p.W), H = uniform(p.H);
+    const int tx = (W + TW - 1) / TW;
     const int local = t - start[i];
-    describe_mask_tile<NW, TW>(tile, p.packedL, p.W, p.H, c, p.descL, p.maskL,
-                               (local % tx) * TW, (local / tx) * kDescTH);
+    describe_mask_tile<NW, TW>(tile, uniform(p.packedL), W, H, c, uniform(p.descL),
+                               uniform(p.maskL), (local % tx) * TW, (local / tx) * kDescTH);
   }
 }
 
