@@ -787,7 +787,7 @@ __device__ __forceinline__ void cost_tile(uint64_t *win, const uint64_t *__restr
 }
 
 template <int NW, int DC, bool MASK, bool VOL>
-__global__ __launch_bounds__(64) void k_cost_wta_fast(const uint64_t *__restrict__ descL,
+__global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restrict__ descL,
                                                       const uint64_t *__restrict__ maskL,
                                                       const uint64_t *__restrict__ descR, int W,
                                                       int H, int dmax, int32_t *__restrict__ disp,
@@ -1210,7 +1210,7 @@ __device__ __forceinline__ int wave_take(int *counter) {
 // claimed before the current tile runs, so the atomic's latency is hidden,
 // and the owning pair is looked up again only when an item leaves it.
 template <int NW, int DC, bool MASK, bool VOL>
-__global__ __launch_bounds__(64) void k_batch_cost(const BatchWork *__restrict__ bw) {
+__global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restrict__ bw) {
   extern __shared__ uint64_t win[];
   const int home = blockIdx.x % kXcds;
   const int n = bw->npairs;
