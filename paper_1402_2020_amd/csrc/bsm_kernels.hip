@@ -422,25 +422,33 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
 }
 
 // ===========================================================================
-// Descriptor only (the non-reference view).  Here the lanes run over 64
-// consecutive pixels of a row and the point pairs are walked in a uniform
-// loop: for pair i all lanes read the intensity at the same offset from
-// their own pixel, i.e. 64 consecutive bytes of an LDS intensity tile, which
-// is free of bank conflicts.  The pair offsets (bytes in the tile) are
-// staged in LDS and read back as broadcasts.  Each lane shifts its binary
-// tests into its own descriptor words, most significant pair first, so that
-// pair 64 j + 32 h + b ends at bit b of half h of word j.  Finished words
-// are staged in LDS per row and written out as whole 128-byte lines.
+// Descriptor only (the non-reference view).  One wave per row of a tile of
+// 256 pixels; lane l owns the four adjacent pixels 4 l .. 4 l + 3 and the
+// point pairs are walked in a uniform loop.  The intensity tile sits in LDS
+// one byte per pixel, its interior starting on a 4-byte boundary and its
+// pitch a multiple of 4, so for pair i the four samples x + p_i of a lane's
+// pixels are 4 consecutive bytes at the same alignment in every lane: two
+// aligned dword reads and one v_alignbyte (shift = the offset's low two
+// bits, wave-uniform) fetch all four.  The pair offsets (bytes in the tile)
+// are wave-uniform and come through scalar loads.  Each pixel's binary
+// tests go bit by bit into its own register with v_alignbit, most
+// significant pair first, so pair 64 j + 32 h + b ends at bit b of half h
+// of word j.  Finished words are staged in LDS as [word][pixel] and written
+// out pixel by pixel as 16-byte chunks.
 // ===========================================================================
-constexpr int kRightTW = 64, kRightTH = 4, kRightThreads = 256;
-constexpr int kRightGroup = 16;                    // words staged per pixel at a time
-constexpr int kRightStagePitch = kRightGroup + 1;  // u64 per staged pixel (odd: fewer conflicts)
+constexpr int kRightPx = 4;                         // pixels per lane (wide tiles)
+constexpr int kRightTW = 64 * kRightPx, kRightTH = 4, kRightThreads = 256;
+constexpr int kRightGroup = 2;                      // words staged per pixel at a time
+// Images with fewer wide tiles than this run one pixel per lane (64-pixel
+// tiles), which gives four times as many workgroups.
+constexpr int kRightWideMinBlocks = 1024;
 
-// LDS bytes of the describe-only kernels: pair offsets, per-wave output
-// staging, intensity tile.
-__host__ __device__ constexpr size_t right_lds_bytes(int n, int radius, int pitch) {
-  return (size_t)n * sizeof(int2) +
-         (size_t)(kRightThreads / 64) * kRightTW * kRightStagePitch * sizeof(uint64_t) +
+__host__ __device__ constexpr int right_halo(int radius) { return (radius + 3) / 4 * 4; }
+
+// LDS bytes of the describe-only kernels: per-wave output staging, then the
+// intensity tile (pitch bytes per row).
+__host__ __device__ constexpr size_t right_lds_bytes(int radius, int pitch) {
+  return (size_t)(kRightThreads / 64) * kRightGroup * kRightTW * sizeof(uint64_t) +
          (size_t)(kRightTH + 2 * radius) * pitch;
 }
 
@@ -449,23 +457,31 @@ struct RightConsts {
   int n, nw, radius, pitch;
 };
 
-// Copies the offset table to the start of LDS (once per block).
-__device__ __forceinline__ void stage_right_offsets(int2 *lds_offs, const RightConsts &c) {
-  for (int i = threadIdx.x; i < c.n; i += kRightThreads) lds_offs[i] = c.offs[i];
+// Bytes x + 0 .. x + PX - 1 of the tile at byte address a + o, where a is a
+// multiple of 4: for PX = 4 two aligned dwords and a funnel shift by
+// o mod 4, for PX = 1 one byte.
+template <int PX>
+__device__ __forceinline__ uint32_t tile_bytes(const uint8_t *tile, int a, int o) {
+  if constexpr (PX == 1) {
+    return tile[a + o];
+  } else {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(tile + a + (o & ~3));
+    return __builtin_amdgcn_alignbyte(w[1], w[0], static_cast<uint32_t>(o & 3));
+  }
 }
 
-__device__ __forceinline__ void describe_right_tile(int2 *lds_offs,
-                                                    const uint32_t *__restrict__ packed, int W,
-                                                    int H, const RightConsts &c,
+template <int PX>
+__device__ __forceinline__ void describe_right_tile(uint8_t *lds, const uint32_t *__restrict__ packed,
+                                                    int W, int H, const RightConsts &c,
                                                     uint64_t *__restrict__ desc, int u0, int v0) {
+  constexpr int TW = 64 * PX;
   const int radius = c.radius, pitch = c.pitch, nw = c.nw;
-  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds_offs + c.n);
-  uint8_t *itile = reinterpret_cast<uint8_t *>(
-      stage_all + (kRightThreads / 64) * kRightTW * kRightStagePitch);
-  const int2 *offs = lds_offs;
-  const int rows = kRightTH + 2 * radius, cols = kRightTW + 2 * radius;
+  const int hx = right_halo(radius);  // tile column of pixel u0
+  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds);
+  uint8_t *itile = lds + (size_t)(kRightThreads / 64) * kRightGroup * kRightTW * sizeof(uint64_t);
+  const int rows = kRightTH + 2 * radius, cols = hx + TW + radius;
   const int total = rows * cols;
-  __syncthreads();  // offsets staged; the previous tile is done with LDS
+  __syncthreads();  // the previous tile is done with LDS
   constexpr int kBatch = 8;
   for (int first = threadIdx.x; first < total; first += kRightThreads * kBatch) {
     uint32_t staged[kBatch];
@@ -476,7 +492,7 @@ __device__ __forceinline__ void describe_right_tile(int2 *lds_offs,
       if (i < total) {
         const int ty = i / cols, tx = i - ty * cols;
         const int gv = min(max(v0 - radius + ty, 0), H - 1);
-        const int gu = min(max(u0 - radius + tx, 0), W - 1);
+        const int gu = min(max(u0 - hx + tx, 0), W - 1);
         staged[b] = packed[(size_t)gv * W + gu];
       }
     }
@@ -491,63 +507,62 @@ __device__ __forceinline__ void describe_right_tile(int2 *lds_offs,
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t *stage = stage_all + wave * kRightTW * kRightStagePitch;
-  constexpr int kRowsPerWave = kRightTH / (kRightThreads / 64);
-  const int valid = min(kRightTW, W - u0);  // pixels of this tile inside the image
-  for (int r = 0; r < kRowsPerWave; ++r) {
-    const int ty = wave * kRowsPerWave + r, v = v0 + ty;
-    if (v >= H) break;  // uniform
-    const uint8_t *centre = itile + (ty + radius) * pitch + (lane + radius);
-    uint64_t *row_out = desc + ((size_t)v * W + u0) * nw;
-    const int G = min(nw, kRightGroup);
-    for (int g0 = 0; g0 < nw; g0 += G) {
-      for (int jj = 0; jj < G; ++jj) {
-        const int j = g0 + jj;
-        uint32_t half[2];
+  uint64_t *stage = stage_all + wave * kRightGroup * TW;
+  const int ty = wave, v = v0 + ty;  // one row per wave
+  if (v >= H) return;                // no barrier follows in this tile
+  const int valid = min(TW, W - u0);  // pixels of this tile inside the image
+  const int base = (ty + radius) * pitch + hx + PX * lane;  // multiple of 4
+  uint64_t *row_out = desc + ((size_t)v * W + u0) * nw;
+  const int2 *__restrict__ offs = c.offs;
+  for (int g0 = 0; g0 < nw; g0 += kRightGroup) {
+    const int G = min(kRightGroup, nw - g0);
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = g0 + jj;
+      uint32_t half[2][PX];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          uint32_t acc = 0;
+      for (int h = 0; h < 2; ++h) {
+        uint32_t acc[PX] = {};
+#pragma unroll 8
+        for (int b = 31; b >= 0; --b) {
+          const int2 o = offs[64 * j + 32 * h + b];  // uniform: scalar load
+          const uint32_t P = tile_bytes<PX>(itile, base, o.x);
+          const uint32_t Q = tile_bytes<PX>(itile, base, o.y);
 #pragma unroll
-          for (int b = 31; b >= 0; --b) {
-            const int2 o = offs[64 * j + 32 * h + b];
+          for (int k = 0; k < PX; ++k) {
             // tau of Eq. 3: for bytes p, q the difference q - p has bit 31
             // set exactly when p > q; alignbit shifts that bit into acc.
-            const uint32_t diff = static_cast<uint32_t>(centre[o.y]) - centre[o.x];
-            acc = __builtin_amdgcn_alignbit(acc, diff, 31);
+            const uint32_t diff = ((Q >> (8 * k)) & 0xffu) - ((P >> (8 * k)) & 0xffu);
+            acc[k] = __builtin_amdgcn_alignbit(acc[k], diff, 31);
           }
-          half[h] = acc;
         }
-        stage[lane * kRightStagePitch + jj] = (static_cast<uint64_t>(half[1]) << 32) | half[0];
+#pragma unroll
+        for (int k = 0; k < PX; ++k) half[h][k] = acc[k];
       }
-      // Copy the group out: pixel p's words g0 .. g0+G-1 are contiguous in
-      // global memory, so consecutive lanes write consecutive 16-byte chunks
-      // (the staging writes and reads are by the same wave, in order).
-      if (G % 2 == 0) {
-        const int per_px = G / 2, chunks = valid * per_px;
-        for (int q = lane; q < chunks; q += 64) {
-          const int p = q / per_px, part = q - p * per_px;
-          const uint64_t *src = stage + p * kRightStagePitch + 2 * part;
-          *reinterpret_cast<ulonglong2 *>(row_out + (size_t)p * nw + g0 + 2 * part) =
-              make_ulonglong2(src[0], src[1]);
-        }
-      } else {
-        const int chunks = valid * G;
-        for (int q = lane; q < chunks; q += 64) {
-          const int p = q / G, part = q - p * G;
-          row_out[(size_t)p * nw + g0 + part] = stage[p * kRightStagePitch + part];
-        }
-      }
+#pragma unroll
+      for (int k = 0; k < PX; ++k)
+        stage[jj * TW + PX * lane + k] =
+            (static_cast<uint64_t>(half[1][k]) << 32) | half[0][k];
+    }
+    // Copy the group out: pixel p's words g0 .. g0+G-1 are contiguous in
+    // global memory (the staging writes and reads are by the same wave, in
+    // order).
+    if (G == 2) {
+      for (int p = lane; p < valid; p += 64)
+        *reinterpret_cast<ulonglong2 *>(row_out + (size_t)p * nw + g0) =
+            make_ulonglong2(stage[p], stage[TW + p]);
+    } else {
+      for (int p = lane; p < valid; p += 64) row_out[(size_t)p * nw + g0] = stage[p];
     }
   }
 }
 
+template <int PX>
 __global__ __launch_bounds__(kRightThreads) void k_describe_right(
     const uint32_t *__restrict__ packed, int W, int H, RightConsts c,
     uint64_t *__restrict__ desc) {
-  extern __shared__ int2 lds_offs[];
-  stage_right_offsets(lds_offs, c);
-  describe_right_tile(lds_offs, packed, W, H, c, desc, blockIdx.x * kRightTW,
-                      blockIdx.y * kRightTH);
+  extern __shared__ uint8_t rlds[];
+  describe_right_tile<PX>(rlds, packed, W, H, c, desc, blockIdx.x * 64 * PX,
+                          blockIdx.y * kRightTH);
 }
 
 // ===========================================================================
@@ -1176,9 +1191,8 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe_mask(
 // when the mask is off.
 __global__ __launch_bounds__(kRightThreads) void k_batch_describe_right(
     const BatchWork *__restrict__ bw, RightConsts c) {
-  extern __shared__ int2 lds_offs[];
+  extern __shared__ uint8_t rlds[];
   __shared__ int slot;
-  stage_right_offsets(lds_offs, c);
   const int *start = bw->start + kQueueDescribe * (bw->npairs + 1);
   const int total = start[bw->npairs];
   for (;;) {
@@ -1186,11 +1200,12 @@ __global__ __launch_bounds__(kRightThreads) void k_batch_describe_right(
     if (t >= total) break;
     const int i = owner(start, bw->npairs, t);
     const BatchPair &p = bw->pairs[bw->order[i]];
-    const int tx = (p.W + kRightTW - 1) / kRightTW, ty = (p.H + kRightTH - 1) / kRightTH;
+    const int W = uniform(p.W), H = uniform(p.H);
+    const int tx = (W + kRightTW - 1) / kRightTW, ty = (H + kRightTH - 1) / kRightTH;
     const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
     // view 0 is the right view; view 1 (mask off only) the left view
-    describe_right_tile(lds_offs, view ? p.packedL : p.packedR, p.W, p.H, c,
-                        view ? p.descL : p.descR, (tile % tx) * kRightTW,
+    describe_right_tile<kRightPx>(rlds, uniform(view ? p.packedL : p.packedR), W, H, c,
+                        uniform(view ? p.descL : p.descR), (tile % tx) * kRightTW,
                         (tile / tx) * kRightTH);
   }
 }
@@ -1345,7 +1360,7 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
   {
     static const hipError_t attr = allow_big_lds(reinterpret_cast<const void *>(k_batch_describe_right));
     if (attr != hipSuccess) return attr;
-    const size_t lds = right_lds_bytes(t.n, t.radius, t.right_pitch);
+    const size_t lds = right_lds_bytes(t.radius, t.right_pitch);
     const int g2 = persistent_grid(k_batch_describe_right, kRightThreads, lds, tu.blocks_per_cu[2]);
     hipLaunchKernelGGL(k_batch_describe_right, dim3(g2), dim3(kRightThreads), lds, s, bw,
                        right_consts(t));
@@ -1388,7 +1403,11 @@ hipError_t launch_batch_nw(const BatchLaunch &bl, const DeviceTables &t, int use
 }  // namespace
 
 int describe_left_cols(int radius, int tile_w) { return tile_w + 2 * radius; }
-int describe_right_cols(int radius) { return kRightTW + 2 * radius; }
+// Row pitch (bytes) of the intensity tile: halo rounded up to 4, the tile,
+// the right halo and one dword of slack for the funnel reads, rounded to 4.
+int describe_right_cols(int radius) {
+  return (right_halo(radius) + kRightTW + radius + 4 + 3) / 4 * 4;
+}
 
 void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
                        int counts[kBatchQueues]) {
@@ -1453,12 +1472,22 @@ hipError_t launch_lr_check(const int32_t *dL, const int32_t *dR, int W, int H, i
 hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTables &t,
                            uint64_t *desc, uint64_t *mask, hipStream_t s) {
   if (!mask) {
-    static const hipError_t attr = allow_big_lds(reinterpret_cast<const void *>(k_describe_right));
-    if (attr != hipSuccess) return attr;
-    const size_t lds = right_lds_bytes(t.n, t.radius, t.right_pitch);
-    dim3 grid((W + kRightTW - 1) / kRightTW, (H + kRightTH - 1) / kRightTH);
-    hipLaunchKernelGGL(k_describe_right, grid, dim3(kRightThreads), lds, s, packed, W, H,
-                       right_consts(t), desc);
+    static const hipError_t attr1 =
+        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<1>));
+    static const hipError_t attr4 =
+        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<kRightPx>));
+    if (attr1 != hipSuccess) return attr1;
+    if (attr4 != hipSuccess) return attr4;
+    const size_t lds = right_lds_bytes(t.radius, t.right_pitch);
+    const int rows = (H + kRightTH - 1) / kRightTH;
+    const int wide = (W + kRightTW - 1) / kRightTW;
+    if ((long long)wide * rows >= kRightWideMinBlocks) {
+      hipLaunchKernelGGL(k_describe_right<kRightPx>, dim3(wide, rows), dim3(kRightThreads), lds,
+                         s, packed, W, H, right_consts(t), desc);
+    } else {
+      hipLaunchKernelGGL(k_describe_right<1>, dim3((W + 63) / 64, rows), dim3(kRightThreads),
+                         lds, s, packed, W, H, right_consts(t), desc);
+    }
     return hipGetLastError();
   }
   if (t.nw <= 1) return launch_describe_mask_nw<1>(packed, W, H, t, desc, mask, s);
