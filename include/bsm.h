@@ -220,13 +220,14 @@ bsm_status bsm_vote_refine(bsm_ctx *ctx, const uint8_t *left, int32_t W,
 
 /* Many pairs of uneven size and dmax at once.  The tiles of all pairs go
  * into device work queues (largest pair first) served by one persistent
- * kernel per stage (colour, describe+mask, describe, cost+WTA); the four
- * launches are captured once per context into a HIP graph that every later
- * batch replays, whatever its shapes.  All pointers in `pairs` are device
- * pointers; `pairs` itself is host memory.  Results equal npairs calls of
- * bsm_match.  Needs n in {64, 128, 256, 512, 1024}; other n run the pairs
- * one after another.  Uses context scratch (the sum of the pairs'
- * bsm_footprint without volumes). */
+ * kernel per stage (colour, describe+mask, describe, cost+WTA with and
+ * without volume); the launches are captured once per context into a HIP
+ * graph that every later batch replays, whatever its shapes.  All pointers
+ * in `pairs` are device pointers; `pairs` itself is host memory.  Results
+ * equal npairs calls of bsm_match.  The persistent path needs n in
+ * {64, 128, 256, 512, 1024} and at least two pairs; otherwise the pairs run
+ * one after another with the per-pair kernels.  Uses context scratch (the
+ * sum of the pairs' bsm_footprint without volumes). */
 bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs,
                            int32_t npairs, void *hip_stream);
 

@@ -275,6 +275,7 @@ class Context:
         self.n = n_bits
         self.nw = n_bits // 64
         self.window = window
+        self._serving = {}  # ticket -> host arrays kept alive until reported
         self.device = device
         self.use_mask = bool(use_mask)
         self.h = bsm_create(n_bits, window, sigma, seed, pattern, mask_rank, use_mask, device)
@@ -446,8 +447,6 @@ class Context:
         ticket.  The arrays and the result buffers stay referenced here until
         the ticket is reported done or failed by poll()."""
         import numpy as np
-        if not hasattr(self, "_serving"):
-            self._serving = {}
         L = np.ascontiguousarray(left, dtype=np.uint8)
         R = np.ascontiguousarray(right, dtype=np.uint8)
         if L.ndim != 3 or L.shape[2] != 3 or R.shape != L.shape:

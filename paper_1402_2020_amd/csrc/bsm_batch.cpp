@@ -102,7 +102,7 @@ bsm_status validate_pairs(const bsm_pair *pairs, int npairs) {
   return BSM_OK;
 }
 
-// Pairs one after another (n outside the batch kernels' range).
+// Pairs one after another with the per-pair kernels.
 bsm_status batch_sequential(bsm_ctx *ctx, BatchState &b, const bsm_pair *pairs, int npairs,
                             hipStream_t s) {
   size_t need = 0;
@@ -264,7 +264,9 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
 
 bsm_status batch_run(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt, const bsm_pair *pairs,
                      int npairs, hipStream_t s) {
-  if (!batch_supported(ctx->nw)) return batch_sequential(ctx, b, pairs, npairs, s);
+  // A single pair gains nothing from the shared work queues: it takes the
+  // per-pair kernels (identical results).
+  if (!batch_supported(ctx->nw) || npairs == 1) return batch_sequential(ctx, b, pairs, npairs, s);
   return batch_persistent(ctx, b, dt, pairs, npairs, s);
 }
 

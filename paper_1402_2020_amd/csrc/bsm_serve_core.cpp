@@ -171,7 +171,7 @@ void Server::loop() {
       if (group.empty()) {
         // Nothing to start: sleep until a submit, or briefly while work runs.
         if (busy)
-          wake_.wait_until(lk, WaitClock::now() + std::chrono::microseconds(50));
+          wake_.wait_until(lk, WaitClock::now() + std::chrono::microseconds(20));
         else if (waiting_.empty() || free_slot < 0)
           wake_.wait_until(lk, WaitClock::now() + std::chrono::milliseconds(5),
                            [this] { return stop_ || !waiting_.empty(); });

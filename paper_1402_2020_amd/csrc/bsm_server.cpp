@@ -20,9 +20,11 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Pinned host buffers kept for reuse, keyed by size.
+// Pinned host buffers kept for reuse, keyed by size.  At most kCachedBytes
+// of idle buffers are kept; beyond that a returned buffer is freed.
 class PinnedPool {
  public:
+  static constexpr size_t kCachedBytes = size_t(2) << 30;
   ~PinnedPool() {
     for (auto &kv : free_)
       for (void *p : kv.second) (void)hipHostFree(p);
@@ -33,6 +35,7 @@ class PinnedPool {
     if (it != free_.end() && it->first <= 2 * bytes && !it->second.empty()) {
       void *p = it->second.back();
       it->second.pop_back();
+      cached_ -= it->first;
       size_[p] = it->first;
       return p;
     }
@@ -43,13 +46,22 @@ class PinnedPool {
   }
   void put(void *p) {
     std::lock_guard<std::mutex> lk(mu_);
-    free_[size_[p]].push_back(p);
+    auto it = size_.find(p);
+    const size_t bytes = it->second;
+    size_.erase(it);
+    if (cached_ + bytes > kCachedBytes) {
+      (void)hipHostFree(p);
+      return;
+    }
+    free_[bytes].push_back(p);
+    cached_ += bytes;
   }
 
  private:
   std::mutex mu_;
-  std::map<size_t, std::vector<void *>> free_;
-  std::map<void *, size_t> size_;
+  std::map<size_t, std::vector<void *>> free_;  // idle buffers by size
+  std::map<void *, size_t> size_;               // buffers handed out
+  size_t cached_ = 0;                           // bytes in free_
 };
 
 // A few host threads that run copy tasks beside the calling thread.  Host

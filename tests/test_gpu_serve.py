@@ -190,3 +190,40 @@ def test_serve_invalid_arguments(torch_cuda, bsm, orc):
         ctx.poll(99)
     assert e.value.status == bsm.ENOTFOUND
     ctx.close()
+
+
+def test_serve_concurrent_clients(torch_cuda, bsm, orc):
+    # several host threads submit and poll at once (the serving calls lock
+    # internally); every result equals the single-pair path's
+    import threading
+    torch = torch_cuda
+    _say("case: serving, 3 client threads x 6 pairs, n=256 S=15")
+    ctx, _ = _ctx(bsm, orc, 256, 15)
+    scenes = _scenes(6, 0.12, first=40)
+    want = []
+    for s in scenes:
+        d, _ = ctx.match(torch.from_numpy(s.left).cuda(), torch.from_numpy(s.right).cuda(), s.dmax)
+        want.append(d.cpu().numpy())
+    errors = []
+
+    def client(c):
+        try:
+            for rep in range(2):
+                ts = [(j, ctx.submit(s.left, s.right, s.dmax)) for j, s in enumerate(scenes)]
+                for j, t in ts:
+                    state, _, (disp, _) = _wait(ctx, t)
+                    if state != 1 or not np.array_equal(disp, want[j]):
+                        errors.append((c, rep, j, state))
+        except Exception as e:  # reported below
+            errors.append((c, repr(e)))
+
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(3)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors[:5]
+    st = ctx.serve_stats()
+    assert st["completed"] == 36 and st["failed"] == 0
+    ctx.close()
