@@ -423,33 +423,40 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
 
 // ===========================================================================
 // Descriptor only (the non-reference view).  One wave per row of a tile of
-// 256 pixels; lane l owns the four adjacent pixels 4 l .. 4 l + 3 and the
-// point pairs are walked in a uniform loop.  The intensity tile sits in LDS
-// one byte per pixel, its interior starting on a 4-byte boundary and its
-// pitch a multiple of 4, so for pair i the four samples x + p_i of a lane's
-// pixels are 4 consecutive bytes at the same alignment in every lane: two
-// aligned dword reads and one v_alignbyte (shift = the offset's low two
-// bits, wave-uniform) fetch all four.  The pair offsets (bytes in the tile)
-// are wave-uniform and come through scalar loads.  Each pixel's binary
-// tests go bit by bit into its own register with v_alignbit, most
-// significant pair first, so pair 64 j + 32 h + b ends at bit b of half h
-// of word j.  Finished words are staged in LDS as [word][pixel] and written
-// out pixel by pixel as 16-byte chunks.
+// 64 PX pixels; lane l owns the PX adjacent pixels PX l .. PX l + PX - 1 and
+// the point pairs are walked in a uniform loop.  The intensity tile sits in
+// LDS one byte per pixel, its interior starting on a 4-byte boundary and
+// its pitch a multiple of 4, so for pair i the PX samples x + p_i of a
+// lane's pixels are PX consecutive bytes at the same alignment in every
+// lane: (PX = 4) two aligned dword reads and one v_alignbyte (shift = the
+// offset's low two bits, wave-uniform) fetch all four.  The pair offsets
+// (bytes in the tile) are wave-uniform and come through scalar loads.  Each
+// pixel's binary tests go bit by bit into its own registers with
+// v_alignbit, most significant pair first, so pair 64 j + 32 h + b ends at
+// bit b of half h of word j.  With one pixel per lane the words are
+// produced 16 at a time (128 bytes of the pixel's string) and stored
+// straight from registers; with four pixels per lane (which would need 128
+// registers for that) every two finished words are staged in LDS as
+// [word][pixel] and written out pixel by pixel as 16-byte chunks.
 // ===========================================================================
 constexpr int kRightPx = 4;                         // pixels per lane (wide tiles)
 constexpr int kRightTW = 64 * kRightPx, kRightTH = 4, kRightThreads = 256;
-constexpr int kRightGroup = 2;                      // words staged per pixel at a time
+constexpr int kRightGroup = 16;                     // words per pass (one pixel per lane)
+constexpr int kRightStageWords = 2;                 // words per LDS stage (four per lane)
 // Images with fewer wide tiles than this run one pixel per lane (64-pixel
 // tiles), which gives four times as many workgroups.
 constexpr int kRightWideMinBlocks = 1024;
 
 __host__ __device__ constexpr int right_halo(int radius) { return (radius + 3) / 4 * 4; }
 
-// LDS bytes of the describe-only kernels: per-wave output staging, then the
-// intensity tile (pitch bytes per row).
-__host__ __device__ constexpr size_t right_lds_bytes(int radius, int pitch) {
-  return (size_t)(kRightThreads / 64) * kRightGroup * kRightTW * sizeof(uint64_t) +
-         (size_t)(kRightTH + 2 * radius) * pitch;
+// LDS bytes of the describe-only kernels with PX pixels per lane: the
+// output staging (four pixels per lane only), then the intensity tile
+// (pitch bytes per row).
+__host__ __device__ constexpr size_t right_stage_bytes(int px) {
+  return px == 1 ? 0 : (size_t)(kRightThreads / 64) * kRightStageWords * 64 * px * sizeof(uint64_t);
+}
+__host__ __device__ constexpr size_t right_lds_bytes(int px, int radius, int pitch) {
+  return right_stage_bytes(px) + (size_t)(kRightTH + 2 * radius) * pitch;
 }
 
 struct RightConsts {
@@ -471,14 +478,15 @@ __device__ __forceinline__ uint32_t tile_bytes(const uint8_t *tile, int a, int o
 }
 
 template <int PX>
-__device__ __forceinline__ void describe_right_tile(uint8_t *lds, const uint32_t *__restrict__ packed,
-                                                    int W, int H, const RightConsts &c,
+__device__ __forceinline__ void describe_right_tile(uint8_t *lds,
+                                                    const uint32_t *__restrict__ packed, int W,
+                                                    int H, const RightConsts &c,
                                                     uint64_t *__restrict__ desc, int u0, int v0) {
   constexpr int TW = 64 * PX;
+  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds);
+  uint8_t *itile = lds + right_stage_bytes(PX);
   const int radius = c.radius, pitch = c.pitch, nw = c.nw;
   const int hx = right_halo(radius);  // tile column of pixel u0
-  uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds);
-  uint8_t *itile = lds + (size_t)(kRightThreads / 64) * kRightGroup * kRightTW * sizeof(uint64_t);
   const int rows = kRightTH + 2 * radius, cols = hx + TW + radius;
   const int total = rows * cols;
   __syncthreads();  // the previous tile is done with LDS
@@ -507,51 +515,91 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds, const uint32_t
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t *stage = stage_all + wave * kRightGroup * TW;
   const int ty = wave, v = v0 + ty;  // one row per wave
   if (v >= H) return;                // no barrier follows in this tile
-  const int valid = min(TW, W - u0);  // pixels of this tile inside the image
-  const int base = (ty + radius) * pitch + hx + PX * lane;  // multiple of 4
-  uint64_t *row_out = desc + ((size_t)v * W + u0) * nw;
+  const int base = (ty + radius) * pitch + hx + PX * lane;  // multiple of 4 for PX = 4
+  const int px0 = u0 + PX * lane;                           // the lane's first pixel
   const int2 *__restrict__ offs = c.offs;
-  for (int g0 = 0; g0 < nw; g0 += kRightGroup) {
-    const int G = min(kRightGroup, nw - g0);
-    for (int jj = 0; jj < G; ++jj) {
-      const int j = g0 + jj;
-      uint32_t half[2][PX];
+  if constexpr (PX == 1) {
+    uint64_t *out = desc + ((size_t)v * W + px0) * nw;
+    for (int g0 = 0; g0 < nw; g0 += kRightGroup) {
+      uint32_t acc[kRightGroup][2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint32_t acc[PX] = {};
+      for (int jj = 0; jj < kRightGroup; ++jj) {
+        if (g0 + jj >= nw) break;  // uniform
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          acc[jj][h] = 0;
 #pragma unroll 8
-        for (int b = 31; b >= 0; --b) {
-          const int2 o = offs[64 * j + 32 * h + b];  // uniform: scalar load
-          const uint32_t P = tile_bytes<PX>(itile, base, o.x);
-          const uint32_t Q = tile_bytes<PX>(itile, base, o.y);
-#pragma unroll
-          for (int k = 0; k < PX; ++k) {
+          for (int b = 31; b >= 0; --b) {
+            const int2 o = offs[64 * (g0 + jj) + 32 * h + b];  // uniform: scalar load
             // tau of Eq. 3: for bytes p, q the difference q - p has bit 31
             // set exactly when p > q; alignbit shifts that bit into acc.
-            const uint32_t diff = ((Q >> (8 * k)) & 0xffu) - ((P >> (8 * k)) & 0xffu);
-            acc[k] = __builtin_amdgcn_alignbit(acc[k], diff, 31);
+            const uint32_t diff = tile_bytes<1>(itile, base, o.y) - tile_bytes<1>(itile, base, o.x);
+            acc[jj][h] = __builtin_amdgcn_alignbit(acc[jj][h], diff, 31);
           }
         }
-#pragma unroll
-        for (int k = 0; k < PX; ++k) half[h][k] = acc[k];
       }
+      // the pixel's words g0 .. g0 + G - 1 (contiguous)
+      const int G = min(kRightGroup, nw - g0);
+      if (px0 < W) {
+        uint64_t *dst = out + g0;
+        if ((nw & 1) == 0) {  // 16-byte aligned pairs of words
 #pragma unroll
-      for (int k = 0; k < PX; ++k)
-        stage[jj * TW + PX * lane + k] =
-            (static_cast<uint64_t>(half[1][k]) << 32) | half[0][k];
+          for (int jj = 0; jj < kRightGroup; jj += 2) {
+            if (jj >= G) break;  // uniform
+            *reinterpret_cast<uint4 *>(dst + jj) =
+                make_uint4(acc[jj][0], acc[jj][1], acc[jj + 1][0], acc[jj + 1][1]);
+          }
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < kRightGroup; ++jj) {
+            if (jj >= G) break;  // uniform
+            dst[jj] = (static_cast<uint64_t>(acc[jj][1]) << 32) | acc[jj][0];
+          }
+        }
+      }
     }
-    // Copy the group out: pixel p's words g0 .. g0+G-1 are contiguous in
-    // global memory (the staging writes and reads are by the same wave, in
-    // order).
-    if (G == 2) {
-      for (int p = lane; p < valid; p += 64)
-        *reinterpret_cast<ulonglong2 *>(row_out + (size_t)p * nw + g0) =
-            make_ulonglong2(stage[p], stage[TW + p]);
-    } else {
-      for (int p = lane; p < valid; p += 64) row_out[(size_t)p * nw + g0] = stage[p];
+  } else {
+    uint64_t *stage = stage_all + wave * kRightStageWords * TW;
+    const int valid = min(TW, W - u0);  // pixels of this tile inside the image
+    uint64_t *row_out = desc + ((size_t)v * W + u0) * nw;
+    for (int g0 = 0; g0 < nw; g0 += kRightStageWords) {
+      const int G = min(kRightStageWords, nw - g0);
+      for (int jj = 0; jj < G; ++jj) {
+        const int j = g0 + jj;
+        uint32_t half[2][PX];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          uint32_t acc[PX] = {};
+#pragma unroll 8
+          for (int b = 31; b >= 0; --b) {
+            const int2 o = offs[64 * j + 32 * h + b];  // uniform: scalar load
+            const uint32_t P = tile_bytes<PX>(itile, base, o.x);
+            const uint32_t Q = tile_bytes<PX>(itile, base, o.y);
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+              const uint32_t diff = ((Q >> (8 * k)) & 0xffu) - ((P >> (8 * k)) & 0xffu);
+              acc[k] = __builtin_amdgcn_alignbit(acc[k], diff, 31);
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < PX; ++k) half[h][k] = acc[k];
+        }
+#pragma unroll
+        for (int k = 0; k < PX; ++k)
+          stage[jj * TW + PX * lane + k] = (static_cast<uint64_t>(half[1][k]) << 32) | half[0][k];
+      }
+      // Copy the group out: pixel p's words g0 .. g0+G-1 are contiguous in
+      // global memory (the staging writes and reads are by the same wave,
+      // in order).
+      if (G == 2) {
+        for (int p = lane; p < valid; p += 64)
+          *reinterpret_cast<ulonglong2 *>(row_out + (size_t)p * nw + g0) =
+              make_ulonglong2(stage[p], stage[TW + p]);
+      } else {
+        for (int p = lane; p < valid; p += 64) row_out[(size_t)p * nw + g0] = stage[p];
+      }
     }
   }
 }
@@ -1360,7 +1408,7 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
   {
     static const hipError_t attr = allow_big_lds(reinterpret_cast<const void *>(k_batch_describe_right));
     if (attr != hipSuccess) return attr;
-    const size_t lds = right_lds_bytes(t.radius, t.right_pitch);
+    const size_t lds = right_lds_bytes(kRightPx, t.radius, t.right_pitch);
     const int g2 = persistent_grid(k_batch_describe_right, kRightThreads, lds, tu.blocks_per_cu[2]);
     hipLaunchKernelGGL(k_batch_describe_right, dim3(g2), dim3(kRightThreads), lds, s, bw,
                        right_consts(t));
@@ -1478,15 +1526,16 @@ hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTab
         allow_big_lds(reinterpret_cast<const void *>(k_describe_right<kRightPx>));
     if (attr1 != hipSuccess) return attr1;
     if (attr4 != hipSuccess) return attr4;
-    const size_t lds = right_lds_bytes(t.radius, t.right_pitch);
     const int rows = (H + kRightTH - 1) / kRightTH;
     const int wide = (W + kRightTW - 1) / kRightTW;
     if ((long long)wide * rows >= kRightWideMinBlocks) {
-      hipLaunchKernelGGL(k_describe_right<kRightPx>, dim3(wide, rows), dim3(kRightThreads), lds,
-                         s, packed, W, H, right_consts(t), desc);
+      hipLaunchKernelGGL(k_describe_right<kRightPx>, dim3(wide, rows), dim3(kRightThreads),
+                         right_lds_bytes(kRightPx, t.radius, t.right_pitch), s, packed, W, H,
+                         right_consts(t), desc);
     } else {
       hipLaunchKernelGGL(k_describe_right<1>, dim3((W + 63) / 64, rows), dim3(kRightThreads),
-                         lds, s, packed, W, H, right_consts(t), desc);
+                         right_lds_bytes(1, t.radius, t.right_pitch), s, packed, W, H,
+                         right_consts(t), desc);
     }
     return hipGetLastError();
   }
