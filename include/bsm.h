@@ -171,7 +171,10 @@ bsm_status bsm_cost_wta(bsm_ctx *ctx, const uint64_t *descL,
 /* The whole hot path for one pair: colour pre-pass and descriptors of both
  * views, mask of the left view (if params.use_mask), cost and WTA.
  * left/right: device RGB; disp/cost as in bsm_cost_wta.  Uses context
- * scratch (bsm_footprint bytes). */
+ * scratch (bsm_footprint bytes).  The other view's colour pass and
+ * descriptor run on an internal stream of the context that first waits for
+ * the work already queued on hip_stream, and hip_stream waits for it before
+ * the cost kernel: the call as a whole stays ordered on hip_stream. */
 bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                      int32_t W, int32_t H, int32_t stride, int32_t dmax,
                      int32_t *disp, int16_t *cost, void *hip_stream);

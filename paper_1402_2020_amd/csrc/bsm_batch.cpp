@@ -21,6 +21,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct BatchState {
   Scratch scratch;               // per-pair planes and descriptors
+  SideLane side;                 // other-view stream of the per-pair path
   // d_work and d_counters live in one allocation at a fixed device address:
   // both are baked into the captured graph, so neither may move while the
   // graph exists.  The tables (which grow with the batch) are only reached
@@ -114,7 +115,7 @@ bsm_status batch_sequential(bsm_ctx *ctx, BatchState &b, const bsm_pair *pairs, 
   for (int i = 0; i < npairs; ++i) {
     const bsm_pair &p = pairs[i];
     bsm_status st = match_on_stream(ctx, p.left, p.right, p.width, p.height, p.stride, p.dmax,
-                                    p.disp, p.cost, buf, s);
+                                    p.disp, p.cost, buf, s, &b.side);
     if (st != BSM_OK) return st;
   }
   if ((e = b.scratch.release(s)) != hipSuccess)

@@ -276,7 +276,22 @@ size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H) {
   size_t px = (size_t)W * H;
   size_t plane = round_up(px * 4, 256);
   size_t desc = round_up(px * ctx->nw * 8, 256);
-  return plane + 3 * desc;
+  return 2 * plane + 3 * desc;
+}
+
+SideLane::~SideLane() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+hipError_t SideLane::ensure() {
+  hipError_t e = hipSuccess;
+  if (!fork && (e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return e;
+  if (!join && (e = hipEventCreateWithFlags(&join, hipEventDisableTiming)) != hipSuccess) return e;
+  if (!stream) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+  return e;
 }
 
 // The whole hot path of one pair on stream s; `scratch` holds
@@ -284,15 +299,21 @@ size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H) {
 // reference (partner (u + d, v) in the left view, the right view's mask):
 // that is left-reference matching of the mirrored pair (mirrored right view
 // as reference, mirrored left view as the other) with the mirrored pattern,
-// whose results are reversed back row by row.
+// whose results are reversed back row by row.  With a side lane (and an
+// image large enough) the other view's colour pass and descriptor run
+// there, forked after everything already queued on s and joined back
+// before the cost kernel.
 bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                            int W, int H, int stride, int dmax, int32_t *disp,
-                           int16_t *cost, void *scratch, hipStream_t s, bool right_reference) {
+                           int16_t *cost, void *scratch, hipStream_t s, SideLane *side,
+                           bool right_reference) {
   size_t px = (size_t)W * H;
   char *base = static_cast<char *>(scratch);
-  uint32_t *packed = reinterpret_cast<uint32_t *>(base);
+  const size_t plane = round_up(px * 4, 256);
+  uint32_t *packedA = reinterpret_cast<uint32_t *>(base);
+  uint32_t *packedB = reinterpret_cast<uint32_t *>(base + plane);
   size_t desc_bytes = round_up(px * ctx->nw * 8, 256);
-  uint64_t *descA = reinterpret_cast<uint64_t *>(base + round_up(px * 4, 256));
+  uint64_t *descA = reinterpret_cast<uint64_t *>(base + 2 * plane);
   uint64_t *maskA = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(descA) + desc_bytes);
   uint64_t *descB = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(maskA) + desc_bytes);
   const bool m = ctx->use_mask != 0;
@@ -301,14 +322,28 @@ bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left, const uint8_t *rig
   const uint8_t *other = right_reference ? left : right;
   const int mirror = right_reference ? 1 : 0;
   hipError_t e;
-  if ((e = launch_color(ref, W, H, stride, packed, m, mirror, t, s)) != hipSuccess)
-    return device_fail(ctx, e, "colour pre-pass (reference view)");
-  if ((e = launch_describe(packed, W, H, t, descA, m ? maskA : nullptr, s)) != hipSuccess)
-    return device_fail(ctx, e, "describe (reference view)");
-  if ((e = launch_color(other, W, H, stride, packed, 0, mirror, t, s)) != hipSuccess)
+  hipStream_t so = s;  // stream of the other view
+  // Below ~64 K pixels the kernels are too short for the cross-stream
+  // waits to pay for themselves.
+  constexpr size_t kSideMinPixels = 1 << 16;
+  if (side && px >= kSideMinPixels) {
+    if ((e = side->ensure()) != hipSuccess || (e = hipEventRecord(side->fork, s)) != hipSuccess ||
+        (e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess)
+      return device_fail(ctx, e, "forking the other view's stream");
+    so = side->stream;
+  }
+  if ((e = launch_color(other, W, H, stride, packedB, 0, mirror, t, so)) != hipSuccess)
     return device_fail(ctx, e, "colour pre-pass (other view)");
-  if ((e = launch_describe(packed, W, H, t, descB, nullptr, s)) != hipSuccess)
+  if ((e = launch_describe(packedB, W, H, t, descB, nullptr, so)) != hipSuccess)
     return device_fail(ctx, e, "describe (other view)");
+  if (so != s && (e = hipEventRecord(side->join, so)) != hipSuccess)
+    return device_fail(ctx, e, "joining the other view's stream");
+  if ((e = launch_color(ref, W, H, stride, packedA, m, mirror, t, s)) != hipSuccess)
+    return device_fail(ctx, e, "colour pre-pass (reference view)");
+  if ((e = launch_describe(packedA, W, H, t, descA, m ? maskA : nullptr, s)) != hipSuccess)
+    return device_fail(ctx, e, "describe (reference view)");
+  if (so != s && (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
+    return device_fail(ctx, e, "joining the other view's stream");
   if ((e = launch_cost_wta(descA, m ? maskA : nullptr, descB, W, H, ctx->nw, dmax, disp, cost, t,
                            s)) != hipSuccess)
     return device_fail(ctx, e, "cost + WTA");
@@ -619,7 +654,8 @@ static bsm_status match_entry(bsm_ctx *ctx, const uint8_t *left, const uint8_t *
   hipError_t e;
   void *buf = ctx->match_scratch.acquire(match_scratch_bytes(ctx, W, H), s, &e);
   if (!buf) return device_fail(ctx, e, "match scratch");
-  st = match_on_stream(ctx, left, right, W, H, stride, dmax, disp, cost, buf, s, right_reference);
+  st = match_on_stream(ctx, left, right, W, H, stride, dmax, disp, cost, buf, s, &ctx->side,
+                       right_reference);
   if (st != BSM_OK) return st;
   if ((e = ctx->match_scratch.release(s)) != hipSuccess)
     return device_fail(ctx, e, "match scratch event");

@@ -162,6 +162,20 @@ class Scratch {
   hipStream_t last_ = nullptr;
 };
 
+// A second stream with a fork and a join event.  The two views of a pair
+// are independent until the cost kernel, so the other view's colour pass
+// and descriptor run on the side stream while the reference view's run on
+// the caller's stream: on images too small to fill the GPU alone the two
+// describe kernels then share it.  Created on first use, with default
+// priority; one owner at a time (a context, or one batch state).
+class SideLane {
+ public:
+  ~SideLane();
+  hipError_t ensure();  // creates the stream and events once
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct Server;
 void server_stop(Server *s);
 
@@ -189,6 +203,7 @@ struct bsm_ctx {
   std::mutex tune_mu;  // guards dt.tune between its setters and the serving thread
   bsm::Scratch describe_scratch;  // packed colour plane of bsm_describe
   bsm::Scratch match_scratch;     // planes + descriptors of bsm_match
+  bsm::SideLane side;             // other-view stream of bsm_match
   bool dead = false;
   std::string dead_reason;
   bsm::BatchState *batch = nullptr;
@@ -210,9 +225,11 @@ bool aligned16(const void *p);
 size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H);
 // The context's tables with the mirrored pattern in place of the pattern.
 DeviceTables mirrored_tables(const bsm_ctx *ctx);
+// `side`: a lane for the other view's work (nullptr: everything on s).
 bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left,
                            const uint8_t *right, int W, int H, int stride,
                            int dmax, int32_t *disp, int16_t *cost,
-                           void *scratch, hipStream_t s, bool right_reference = false);
+                           void *scratch, hipStream_t s, SideLane *side,
+                           bool right_reference = false);
 double now_seconds();
 }  // namespace bsm

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL
 //   NW <= 4  lane l of word j owns pair 64 j + l, so the ballot of the
 //            wave's tests IS word j, moved into lane j with v_writelane.
 // ===========================================================================
-constexpr int kDescTH = 8, kDescThreads = 256;
+constexpr int kDescTH = 4, kDescThreads = 256;
 constexpr int kGallopStep = 8;  // first step of the threshold search
 
 // Pair index of slot j of lane `lane` (0-based).
