@@ -131,7 +131,12 @@ __global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL
 //   NW <= 4  lane l of word j owns pair 64 j + l, so the ballot of the
 //            wave's tests IS word j, moved into lane j with v_writelane.
 // ===========================================================================
-constexpr int kDescTH = 4, kDescThreads = 256;
+// Tile height (rows) of the describe+mask tiles: eight rows when the image
+// has tiles enough to fill the GPU several times over (fewer halo rows per
+// output row), four rows otherwise (twice the tiles, shorter tails).  The
+// persistent batch kernel always takes eight.
+constexpr int kDescTH = 8, kDescTHSmall = 4, kDescThreads = 256;
+constexpr long long kDescTallMinTiles = 4096;  // four rounds of the GPU at four blocks per CU
 constexpr int kGallopStep = 8;  // first step of the threshold search
 
 // Pair index of slot j of lane `lane` (0-based).
@@ -330,14 +335,14 @@ struct DescribeConsts {
   int nw, radius, pitch, k;
 };
 
-template <int NW, int TW>
+template <int NW, int TW, int TH>
 __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
                                                    const uint32_t *__restrict__ packed, int W,
                                                    int H, const DescribeConsts &c,
                                                    uint64_t *__restrict__ desc,
                                                    uint64_t *__restrict__ mask, int u0, int v0) {
   const int radius = c.radius, pitch = c.pitch, nw = c.nw, n = 64 * nw;
-  const int rows = kDescTH + 2 * radius, cols = TW + 2 * radius;
+  const int rows = TH + 2 * radius, cols = TW + 2 * radius;
   const int total = rows * cols;
   __syncthreads();  // the previous tile (persistent kernels) is done with LDS
   // Stage the tile with kBatch independent loads in flight per thread.
@@ -385,7 +390,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
   __syncthreads();
 
   const char *lds = reinterpret_cast<const char *>(tile);
-  constexpr int kRowsPerWave = kDescTH / (kDescThreads / 64);
+  constexpr int kRowsPerWave = TH / (kDescThreads / 64);
   constexpr int kGroup = 4;  // pixels whose LDS addresses share one base
   int guess = 64;            // threshold search start: the previous pixel's T
   for (int r = 0; r < kRowsPerWave; ++r) {
@@ -412,13 +417,13 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
   }
 }
 
-template <int NW, int TW>
+template <int NW, int TW, int TH>
 __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
-  describe_mask_tile<NW, TW>(tile, packed, W, H, c, desc, mask, blockIdx.x * TW,
-                             blockIdx.y * kDescTH);
+  describe_mask_tile<NW, TW, TH>(tile, packed, W, H, c, desc, mask, blockIdx.x * TW,
+                                 blockIdx.y * TH);
 }
 
 // ===========================================================================
@@ -1230,7 +1235,7 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe_mask(
     const int W = uniform(p.W), H = uniform(p.H);
     const int tx = (W + TW - 1) / TW;
     const int local = t - start[i];
-    describe_mask_tile<NW, TW>(tile, uniform(p.packedL), W, H, c, uniform(p.descL),
+    describe_mask_tile<NW, TW, kDescTH>(tile, uniform(p.packedL), W, H, c, uniform(p.descL),
                                uniform(p.maskL), (local % tx) * TW, (local / tx) * kDescTH);
   }
 }
@@ -1313,8 +1318,8 @@ RightConsts right_consts(const DeviceTables &t) {
   return RightConsts{t.right_offs, t.n, t.nw, t.radius, t.right_pitch};
 }
 
-size_t mask_lds_bytes(const DeviceTables &t, int tw) {
-  return (size_t)(kDescTH + 2 * t.radius) * t.left_pitch_for(tw) * sizeof(uint32_t);
+size_t mask_lds_bytes(const DeviceTables &t, int tw, int th = kDescTH) {
+  return (size_t)(th + 2 * t.radius) * t.left_pitch_for(tw) * sizeof(uint32_t);
 }
 
 template <int NW, int TW>
@@ -1322,9 +1327,16 @@ hipError_t launch_describe_mask_t(const uint32_t *packed, int W, int H, const De
                                   uint64_t *desc, uint64_t *mask, hipStream_t s) {
   DescribeConsts c = describe_consts(t);
   c.pitch = t.left_pitch_for(TW);
-  dim3 grid((W + TW - 1) / TW, (H + kDescTH - 1) / kDescTH);
-  hipLaunchKernelGGL((k_describe_mask<NW, TW>), grid, dim3(kDescThreads), mask_lds_bytes(t, TW), s,
-                     packed, W, H, c, desc, mask);
+  const long long tall_tiles = (long long)((W + TW - 1) / TW) * ((H + kDescTH - 1) / kDescTH);
+  if (tall_tiles >= kDescTallMinTiles) {
+    dim3 grid((W + TW - 1) / TW, (H + kDescTH - 1) / kDescTH);
+    hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTH>), grid, dim3(kDescThreads),
+                       mask_lds_bytes(t, TW, kDescTH), s, packed, W, H, c, desc, mask);
+  } else {
+    dim3 grid((W + TW - 1) / TW, (H + kDescTHSmall - 1) / kDescTHSmall);
+    hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTHSmall>), grid, dim3(kDescThreads),
+                       mask_lds_bytes(t, TW, kDescTHSmall), s, packed, W, H, c, desc, mask);
+  }
   return hipGetLastError();
 }
 
