@@ -241,6 +241,10 @@ typedef struct {
     int32_t blocks_per_cu[4]; /* workgroups per CU of the persistent batch
                                  stages (colour, describe+mask, describe,
                                  cost); 0 = as many as fit, max 64          */
+    int32_t cost_mfma;        /* 1 (default): cost + WTA without a volume on
+                                 the matrix cores (the cost as an integer
+                                 dot product); 0: the bitwise VALU kernel.
+                                 Calls with a volume always take the latter */
 } bsm_tuning;
 
 bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out);

@@ -377,6 +377,7 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
     best->desc_tile_w = best_t.desc_tile_w;
     best->cost_dchunk = best_t.cost_dchunk;
     for (int i = 0; i < 4; ++i) best->blocks_per_cu[i] = best_t.blocks_per_cu[i];
+    best->cost_mfma = best_t.cost_mfma;
   }
   if (best_ms) *best_ms = best_time;
   return BSM_OK;

@@ -46,6 +46,7 @@ struct Tuning {
   int desc_tile_w = 16;                // describe+mask tile width: 16 or 32 pixels
   int cost_dchunk = 64;                // disparities per cost LDS window: 32 or 64
   int blocks_per_cu[4] = {0, 0, 0, 0};  // persistent batch grids (0: all that fit)
+  int cost_mfma = 1;                    // no-volume cost + WTA on the matrix cores
 };
 
 // Device-side view of the constant data of a context.

@@ -875,6 +875,163 @@ __global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restr
 }
 
 // ===========================================================================
+// Masked cost + WTA on the matrix cores, without a cost volume, n = 64 NW
+// bits, NW in {1, 2, 4, 8, 16}.
+//
+// The masked Hamming distance of Eq. 8 is a dot product.  For bits a (B_L),
+// m (Phi_L) and b (B_R), m (a ^ b) = m a + m (1 - 2a) b, so
+//   popcount((a ^ b) & m) = popcount(a & m) + sum_i v_i b_i,
+// with v_i = m_i (1 - 2 a_i) in {-1, 0, 1}; Eq. 4 is the case m = all ones.
+// For one row, the costs of a tile of 32 left pixels against a block of 32
+// right pixels are therefore one 32 x 32 integer matrix product over the n
+// bits (left v as int8 rows, right bits as int8 columns), started from the
+// per-row constant popcount(a & m).  v_mfma_i32_32x32x32_i8 takes 32 bits per
+// step: lane (c, h) = (l % 32, l / 32) supplies 16 bits of the step's 32-bit
+// slice, one byte per bit, for left pixel u0 + c (A operand, kept in
+// registers for the whole tile) and right pixel r0 + c (B operand, expanded
+// from the packed words at each step).  Which bit sits in which byte is free
+// as long as A and B agree; byte r of dword q holds bit 8r + 4h + q, so that
+// dword q of B is ((x >> 4h) >> q) & 0x01010101: two operations.  Right block q holds the
+// pixels u0 - 32q + j, so entry (i, j) is disparity 32q + i - j, and blocks
+// q = 0 .. Q-1 cover [0, dmax).  The accumulator gives lane (c, h) rows
+// 8(e/4) + 4h + e%4 of column c in its element e; the lane keeps the running
+// minimum of the key (C << 16) | d per element, and a butterfly over the 32
+// columns ends the WTA with the lowest d among equal costs.  The costs are
+// exact integers, so the winners equal the bitwise kernel's.
+// ===========================================================================
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef int v16i32 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaTX = 32;     // left pixels per wave
+constexpr int kMfmaWaves = 4;   // tiles (waves) per workgroup, consecutive in a row
+
+// The 2 NW 32-bit slices of one string (NW 64-bit words at p).
+template <int NW>
+__device__ __forceinline__ void load_slices(const uint64_t *p, uint32_t *out) {
+  if constexpr (NW % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < NW / 2; ++i) {
+      const uint4 x = reinterpret_cast<const uint4 *>(p)[i];
+      out[4 * i] = x.x;
+      out[4 * i + 1] = x.y;
+      out[4 * i + 2] = x.z;
+      out[4 * i + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint2 x = reinterpret_cast<const uint2 *>(p)[i];
+      out[2 * i] = x.x;
+      out[2 * i + 1] = x.y;
+    }
+  }
+}
+
+// Bits q, q + 8, q + 16, q + 24 of y as the four bytes of a dword (0 or 1);
+// `ones` = 0x01010101, or 0 to give zeros.
+__device__ __forceinline__ uint32_t byte_bits(uint32_t y, int q, uint32_t ones = 0x01010101u) {
+  return (y >> q) & ones;
+}
+
+template <int NW, bool MASK>
+__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
+    const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
+    const uint64_t *__restrict__ descR, int W, int H, int dmax, int32_t *__restrict__ disp) {
+  constexpr int kSlices = 2 * NW;  // 32-bit slices of a string
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 31, h = lane >> 5;
+  // XCD-aware order (see k_cost_wta_fast), in groups of kMfmaWaves tiles.
+  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
+  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / groups);
+  const int tile = (slot % groups) * kMfmaWaves + wave;
+  if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
+  const int u0 = tile * kMfmaTX;
+
+  // A operands of the lane's left pixel, and popcount(a & m) of it.  Loads
+  // are unconditional from a clamped pixel (16 bytes at a time; every
+  // string is 8-byte aligned, and 16-byte aligned when NW is even) and
+  // zeroed afterwards, so no load sits behind a branch.
+  const int ua = u0 + c;
+  const bool has_a = ua < W;
+  const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
+  v4i32 A[kSlices];
+  int am = 0;
+  {
+    uint32_t aw[kSlices], mw[kSlices];
+    load_slices<NW>(descL + pa_off, aw);
+    if (MASK) load_slices<NW>(maskL + pa_off, mw);
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      if (!MASK) mw[s] = 0xffffffffu;
+      if (!has_a) aw[s] = mw[s] = 0;
+      const uint32_t x = aw[s] & mw[s];
+      am += __builtin_popcount(x);
+      const uint32_t my = mw[s] >> (4 * h), amy = x >> (4 * h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)  // byte: 1 (m, !a), 0xff (m, a), 0 (!m)
+        A[s][q] = static_cast<int>(byte_bits(my, q) ^ (byte_bits(amy, q) * 0xfeu));
+    }
+  }
+  // Row constants of the lane's accumulator elements.
+  int am_e[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) am_e[e] = __shfl(am, 8 * (e / 4) + 4 * h + (e % 4));
+
+  uint32_t best[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) best[e] = 0xffffffffu;
+  const uint64_t *rowR = descR + (size_t)v * W * NW;
+  const int nq = (dmax + 30) / kMfmaTX + 1;  // right blocks
+  // The lane's right pixel of block q, clamped into the row for loading.
+  auto right_px = [&](int q) { return min(max(u0 - kMfmaTX * q + c, 0), W - 1); };
+  uint32_t bw[kSlices];
+  load_slices<NW>(rowR + (size_t)right_px(0) * NW, bw);
+  for (int q = 0; q < nq; ++q) {
+    const int rb = u0 - kMfmaTX * q + c;  // the lane's right pixel
+    const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;  // missing pixel: B = 0
+    v16i32 acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = am_e[e];
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const uint32_t by = bw[s] >> (4 * h);
+      v4i32 B;
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(byte_bits(by, q4, ones));
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc, 0, 0, 0);
+    }
+    // the next block's words load while this block's products finish
+    if (q + 1 < nq) load_slices<NW>(rowR + (size_t)right_px(q + 1) * NW, bw);
+    // d of element e is dbase + row(e); valid when 0 <= d < dmax and the
+    // right pixel exists (u - d = rb >= 0).
+    const int dbase = kMfmaTX * q - c;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
+      const uint32_t key = (static_cast<uint32_t>(acc[e]) << 16) | static_cast<uint32_t>(d);
+      if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
+    }
+  }
+  // WTA across the 32 columns of each half.
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      best[e] = min(best[e], static_cast<uint32_t>(__shfl_xor(static_cast<int>(best[e]), off)));
+  }
+  if (c < 16) {
+    uint32_t key = best[0];
+#pragma unroll
+    for (int e = 1; e < 16; ++e)
+      if (c == e) key = best[e];
+    const int u = u0 + 8 * (c / 4) + 4 * h + (c % 4);
+    if (u < W) disp[(size_t)v * W + u] = static_cast<int32_t>(key & 0xffffu);
+  }
+}
+
+// ===========================================================================
 // Cost + WTA for any n = 64 nw bits (nw outside the register-resident
 // kernel's set, up to n = 4096).  Same tiling and diagonal reuse as above
 // (one wave per row tile of 128 pixels, lane l owns a = u0 + 2l and b = a +
@@ -1377,6 +1534,21 @@ hipError_t launch_cost_fast_dc(const uint64_t *descL, const uint64_t *maskL,
 }
 
 template <int NW>
+hipError_t launch_cost_mfma(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
+                            int W, int H, int dmax, int32_t *disp, hipStream_t s) {
+  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
+  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+  dim3 grid(kXcds * groups * ((H + kXcds - 1) / kXcds));
+  if (maskL)
+    hipLaunchKernelGGL((k_cost_wta_mfma<NW, true>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
+                       maskL, descR, W, H, dmax, disp);
+  else
+    hipLaunchKernelGGL((k_cost_wta_mfma<NW, false>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
+                       maskL, descR, W, H, dmax, disp);
+  return hipGetLastError();
+}
+
+template <int NW>
 hipError_t launch_cost_fast(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
                             int W, int H, int dmax, int32_t *disp, int16_t *cost, int dc,
                             hipStream_t s) {
@@ -1564,6 +1736,16 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const u
                            int W, int H, int nw, int dmax, int32_t *disp, int16_t *cost,
                            const DeviceTables &t, hipStream_t s) {
   const int dc = t.tune.cost_dchunk;
+  if (!cost && t.tune.cost_mfma) {  // matrix-core kernel (no volume)
+    switch (nw) {
+      case 1: return launch_cost_mfma<1>(descL, maskL, descR, W, H, dmax, disp, s);
+      case 2: return launch_cost_mfma<2>(descL, maskL, descR, W, H, dmax, disp, s);
+      case 4: return launch_cost_mfma<4>(descL, maskL, descR, W, H, dmax, disp, s);
+      case 8: return launch_cost_mfma<8>(descL, maskL, descR, W, H, dmax, disp, s);
+      case 16: return launch_cost_mfma<16>(descL, maskL, descR, W, H, dmax, disp, s);
+      default: break;
+    }
+  }
   switch (nw) {
     case 1: return launch_cost_fast<1>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);
     case 2: return launch_cost_fast<2>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);

@@ -171,6 +171,62 @@ def test_cost_wta_parity(torch_cuda, bsm, orc, W, H, nw, dmax, use_mask, vol):
     ctx.close()
 
 
+MFMA_CASES = [
+    # W, H, nw, dmax, mask
+    (1, 2, 1, 1, True),
+    (31, 3, 2, 31, True),
+    (33, 2, 4, 1, False),
+    (97, 3, 8, 64, True),
+    (130, 2, 16, 33, True),
+    (300, 3, 16, 257, True),
+    (257, 2, 16, 130, False),
+    (64, 4, 16, 64, True),
+    (450, 2, 16, 60, True),
+]
+
+
+@pytest.mark.parametrize("W,H,nw,dmax,use_mask", MFMA_CASES)
+def test_cost_wta_matrix_core_and_bitwise(torch_cuda, bsm, orc, W, H, nw, dmax, use_mask):
+    # without a volume the fused cost + WTA runs on the matrix cores by
+    # default (the cost as an integer dot product); both kernels must give
+    # the oracle's winners
+    torch = torch_cuda
+    _say(f"case: cost_wta no volume, mfma and bitwise, W={W} H={H} nw={nw} dmax={dmax} "
+         f"mask={use_mask}")
+    rng = np.random.Generator(np.random.PCG64(7 * W + H + 13 * nw + dmax))
+    base = rng.integers(0, 2**63, (H, W + dmax, nw), dtype=np.uint64)
+    noise = rng.integers(0, 2**63, (H, W, nw), dtype=np.uint64) & \
+        rng.integers(0, 2**63, (H, W, nw), dtype=np.uint64)
+    shift = int(rng.integers(0, dmax))
+    dr = np.ascontiguousarray(base[:, dmax:dmax + W])
+    dl = np.ascontiguousarray(base[:, dmax - shift:dmax - shift + W] ^ noise)
+    m = rng.integers(0, 2**63, (H, W, nw), dtype=np.uint64) if use_mask else None
+    want = orc.wta(orc.cost_volume(dl, m, dr, dmax))
+    ctx, _ = _ctx(bsm, orc, 64 * nw, 3)
+    t = lambda a: None if a is None else _dev(torch, a.view(np.int64))
+    for mfma in (1, 0):
+        tune = ctx.tuning()
+        tune["cost_mfma"] = mfma
+        ctx.set_tuning(tune)
+        disp, _ = ctx.cost_wta(t(dl), t(m), t(dr), dmax, want_cost=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(disp.cpu().numpy(), want), mfma
+    ctx.close()
+
+
+def test_cost_wta_matrix_core_ties(torch_cuda, bsm, orc):
+    torch = torch_cuda
+    _say("case: matrix-core cost_wta, all-equal and all-different descriptors")
+    ctx, _ = _ctx(bsm, orc, 1024, 3)
+    z = torch.zeros((3, 100, 16), dtype=torch.int64, device="cuda")
+    disp, _ = ctx.cost_wta(z, z, z, 70, want_cost=False)
+    assert not disp.cpu().numpy().any()          # every cost 0: lowest d
+    ones = torch.full((3, 100, 16), -1, dtype=torch.int64, device="cuda")
+    disp, _ = ctx.cost_wta(ones, ones, z, 70, want_cost=False)
+    assert not disp.cpu().numpy().any()          # every cost n: lowest d
+    ctx.close()
+
+
 def test_cost_ties_take_lowest_d(torch_cuda, bsm, orc):
     torch = torch_cuda
     _say("case: all-equal descriptors (every cost 0)")
