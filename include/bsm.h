@@ -238,9 +238,12 @@ bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs,
 typedef struct {
     int32_t desc_tile_w;      /* describe+mask tile width: 16 or 32 pixels   */
     int32_t cost_dchunk;      /* disparities per cost LDS window: 32 or 64  */
-    int32_t blocks_per_cu[4]; /* workgroups per CU of the persistent batch
-                                 stages (colour, describe+mask, describe,
-                                 cost); 0 = as many as fit, max 64          */
+    int32_t blocks_per_cu[4]; /* persistent batch launches, 0 = default:
+                                 [0] colour, [1] the two describe stages
+                                 (one launch), [3] cost: workgroups per CU
+                                 (0 = as many as fit, max 64); [2]: one
+                                 describe workgroup in this many starts on
+                                 the descriptor-only tiles (0 = 4)          */
     int32_t cost_mfma;        /* 1 (default): cost + WTA without a volume on
                                  the matrix cores (the cost as an integer
                                  dot product); 0: the bitwise VALU kernel.

@@ -124,7 +124,9 @@ bsm_status batch_sequential(bsm_ctx *ctx, BatchState &b, const bsm_pair *pairs, 
 }
 
 bool same_tuning(const Tuning &a, const Tuning &b) {
-  if (a.desc_tile_w != b.desc_tile_w || a.cost_dchunk != b.cost_dchunk) return false;
+  if (a.desc_tile_w != b.desc_tile_w || a.cost_dchunk != b.cost_dchunk ||
+      a.cost_mfma != b.cost_mfma)
+    return false;
   for (int i = 0; i < 4; ++i)
     if (a.blocks_per_cu[i] != b.blocks_per_cu[i]) return false;
   return true;
@@ -336,18 +338,19 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
   }
   Tuning best_t = ctx->dt.tune;
   double best_time = -1;
-  // Candidates: describe tile width x cost window x cost / describe+mask
-  // persistent occupancy.  Each runs on a copy of the tables; the batch
-  // state recaptures its graph whenever the launch choices change.
+  // Candidates: describe tile width x cost window (pairs with a volume) x
+  // cost persistent occupancy x share of the describe workgroups that
+  // start on the descriptor-only tiles.  Each runs on a copy of the tables;
+  // the batch state recaptures its graph whenever the launch choices change.
   for (int tw : {16, 32})
     for (int dc : {32, 64})
       for (int cost_bpc : {0, 2})
-        for (int mask_bpc : {0, 2}) {
+        for (int right_every : {4, 8}) {
           DeviceTables dt = ctx->dt;
           dt.tune = Tuning();
           dt.tune.desc_tile_w = tw;
           dt.tune.cost_dchunk = dc;
-          dt.tune.blocks_per_cu[1] = mask_bpc;
+          dt.tune.blocks_per_cu[2] = right_every;
           dt.tune.blocks_per_cu[3] = cost_bpc;
           // one untimed run (captures the graph), then the timed runs
           if ((st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s)) != BSM_OK) break;

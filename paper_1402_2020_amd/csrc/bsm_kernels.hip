@@ -8,8 +8,9 @@
 // Each stage is a per-tile device function.  The single-pair kernels map
 // one workgroup to one tile; the batch kernels are persistent and pull the
 // tiles of many pairs from a device work list, so both paths run the same
-// per-tile code.  Nothing here is a dense contraction, so there is no MFMA:
-// the kernels are bound by integer VALU/SALU issue or by HBM.
+// per-tile code.  The kernels are bound by integer VALU/SALU issue or by
+// HBM, except the cost + WTA without a volume, which runs the masked Hamming
+// cost as an int8 dot product on the matrix cores.
 #include <type_traits>
 
 #include "bsm_internal.h"
@@ -447,6 +448,7 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
 constexpr int kRightPx = 4;                         // pixels per lane (wide tiles)
 constexpr int kRightTW = 64 * kRightPx, kRightTH = 4, kRightThreads = 256;
 constexpr int kRightGroup = 16;                     // words per pass (one pixel per lane)
+constexpr int kDescRightEvery = 4;  // batch: one describe workgroup in this many starts right
 constexpr int kRightStageWords = 2;                 // words per LDS stage (four per lane)
 // Images with fewer wide tiles than this run one pixel per lane (64-pixel
 // tiles), which gives four times as many workgroups.
@@ -882,22 +884,24 @@ __global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restr
 // m (Phi_L) and b (B_R), m (a ^ b) = m a + m (1 - 2a) b, so
 //   popcount((a ^ b) & m) = popcount(a & m) + sum_i v_i b_i,
 // with v_i = m_i (1 - 2 a_i) in {-1, 0, 1}; Eq. 4 is the case m = all ones.
-// For one row, the costs of a tile of 32 left pixels against a block of 32
-// right pixels are therefore one 32 x 32 integer matrix product over the n
-// bits (left v as int8 rows, right bits as int8 columns), started from the
-// per-row constant popcount(a & m).  v_mfma_i32_32x32x32_i8 takes 32 bits per
-// step: lane (c, h) = (l % 32, l / 32) supplies 16 bits of the step's 32-bit
-// slice, one byte per bit, for left pixel u0 + c (A operand, kept in
+// popcount(a & m) is fixed per left pixel and cannot move its minimum over
+// d, so the WTA ranks n + sum_i v_i b_i (in [0, 2n]) instead.  For one row,
+// these sums for a tile of 32 left pixels against a block of 32 right pixels
+// are one 32 x 32 integer matrix product over the n bits: left v as int8
+// rows, right bits as int8 columns.  v_mfma_i32_32x32x32_i8 takes 32 bits
+// per step; lane (c, h) = (l % 32, l / 32) supplies 16 bits of the step's
+// 32-bit slice, one byte per bit, for left pixel u0 + c (A operand, kept in
 // registers for the whole tile) and right pixel r0 + c (B operand, expanded
 // from the packed words at each step).  Which bit sits in which byte is free
-// as long as A and B agree; byte r of dword q holds bit 8r + 4h + q, so that
-// dword q of B is ((x >> 4h) >> q) & 0x01010101: two operations.  Right block q holds the
-// pixels u0 - 32q + j, so entry (i, j) is disparity 32q + i - j, and blocks
-// q = 0 .. Q-1 cover [0, dmax).  The accumulator gives lane (c, h) rows
-// 8(e/4) + 4h + e%4 of column c in its element e; the lane keeps the running
-// minimum of the key (C << 16) | d per element, and a butterfly over the 32
-// columns ends the WTA with the lowest d among equal costs.  The costs are
-// exact integers, so the winners equal the bitwise kernel's.
+// as long as A and B agree: byte r of dword q holds bit 8r + 4h + q, so dword
+// q of B is ((x >> 4h) >> q) & 0x01010101, two operations.  Right block q
+// holds the pixels u0 - 32q + j, so entry (i, j) is disparity 32q + i - j and
+// the blocks q = 0 .. Q-1 cover [0, dmax).  The accumulator gives lane (c, h)
+// row 8(e/4) + 4h + e%4 of column c in its element e; the lane keeps the
+// running minimum of the key (sum << 16) | d per element, and a butterfly
+// over the 32 columns ends the WTA with the lowest d among equal costs.
+// Everything is exact integer arithmetic, so the winners equal the bitwise
+// kernel's.
 // ===========================================================================
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
@@ -933,23 +937,18 @@ __device__ __forceinline__ uint32_t byte_bits(uint32_t y, int q, uint32_t ones =
   return (y >> q) & ones;
 }
 
+// One wave: the 32 left pixels of row v from u0.
 template <int NW, bool MASK>
-__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
-    const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
-    const uint64_t *__restrict__ descR, int W, int H, int dmax, int32_t *__restrict__ disp) {
+__device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ descL,
+                                               const uint64_t *__restrict__ maskL,
+                                               const uint64_t *__restrict__ descR, int W,
+                                               int dmax, int32_t *__restrict__ disp, int v,
+                                               int u0) {
   constexpr int kSlices = 2 * NW;  // 32-bit slices of a string
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int c = lane & 31, h = lane >> 5;
-  // XCD-aware order (see k_cost_wta_fast), in groups of kMfmaWaves tiles.
-  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
-  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
-  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const int v = xcd + kXcds * (slot / groups);
-  const int tile = (slot % groups) * kMfmaWaves + wave;
-  if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
-  const int u0 = tile * kMfmaTX;
 
-  // A operands of the lane's left pixel, and popcount(a & m) of it.  Loads
+  // A operands of the lane's left pixel.  Loads
   // are unconditional from a clamped pixel (16 bytes at a time; every
   // string is 8-byte aligned, and 16-byte aligned when NW is even) and
   // zeroed afterwards, so no load sits behind a branch.
@@ -957,7 +956,6 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
   const bool has_a = ua < W;
   const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
   v4i32 A[kSlices];
-  int am = 0;
   {
     uint32_t aw[kSlices], mw[kSlices];
     load_slices<NW>(descL + pa_off, aw);
@@ -967,18 +965,16 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
       if (!MASK) mw[s] = 0xffffffffu;
       if (!has_a) aw[s] = mw[s] = 0;
       const uint32_t x = aw[s] & mw[s];
-      am += __builtin_popcount(x);
-      const uint32_t my = mw[s] >> (4 * h), amy = x >> (4 * h);
+      // bytes 1 for (m, !a), 0xff for (m, a), 0 for !m: pos + 255 neg, where
+      // 255 neg = (neg << 8) - neg has no carries (each byte of neg is 0 or 1)
+      const uint32_t py = (mw[s] & ~aw[s]) >> (4 * h), ny = x >> (4 * h);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)  // byte: 1 (m, !a), 0xff (m, a), 0 (!m)
-        A[s][q] = static_cast<int>(byte_bits(my, q) ^ (byte_bits(amy, q) * 0xfeu));
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t pos = byte_bits(py, q), neg = byte_bits(ny, q);
+        A[s][q] = static_cast<int>((neg << 8) + pos - neg);
+      }
     }
   }
-  // Row constants of the lane's accumulator elements.
-  int am_e[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) am_e[e] = __shfl(am, 8 * (e / 4) + 4 * h + (e % 4));
-
   uint32_t best[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) best[e] = 0xffffffffu;
@@ -993,7 +989,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
     const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;  // missing pixel: B = 0
     v16i32 acc;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = am_e[e];
+    for (int e = 0; e < 16; ++e) acc[e] = 64 * NW;  // n + sum v b >= 0
 #pragma unroll
     for (int s = 0; s < kSlices; ++s) {
       const uint32_t by = bw[s] >> (4 * h);
@@ -1005,13 +1001,22 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
     // the next block's words load while this block's products finish
     if (q + 1 < nq) load_slices<NW>(rowR + (size_t)right_px(q + 1) * NW, bw);
     // d of element e is dbase + row(e); valid when 0 <= d < dmax and the
-    // right pixel exists (u - d = rb >= 0).
+    // right pixel exists (u - d = rb >= 0).  Blocks whose every entry is
+    // valid (the wave-uniform test below) skip the per-element checks.
     const int dbase = kMfmaTX * q - c;
+    if (q >= 1 && kMfmaTX * q + kMfmaTX - 1 < dmax && u0 - kMfmaTX * q >= 0) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
-      const uint32_t key = (static_cast<uint32_t>(acc[e]) << 16) | static_cast<uint32_t>(d);
-      if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
+      for (int e = 0; e < 16; ++e) {
+        const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
+        best[e] = min(best[e], (static_cast<uint32_t>(acc[e]) << 16) | static_cast<uint32_t>(d));
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
+        const uint32_t key = (static_cast<uint32_t>(acc[e]) << 16) | static_cast<uint32_t>(d);
+        if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
+      }
     }
   }
   // WTA across the 32 columns of each half.
@@ -1029,6 +1034,20 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
     const int u = u0 + 8 * (c / 4) + 4 * h + (c % 4);
     if (u < W) disp[(size_t)v * W + u] = static_cast<int32_t>(key & 0xffffu);
   }
+}
+
+template <int NW, bool MASK>
+__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
+    const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
+    const uint64_t *__restrict__ descR, int W, int H, int dmax, int32_t *__restrict__ disp) {
+  // XCD-aware order (see k_cost_wta_fast), in groups of kMfmaWaves tiles.
+  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
+  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / groups);
+  const int tile = (slot % groups) * kMfmaWaves + (threadIdx.x >> 6);
+  if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
+  cost_tile_mfma<NW, MASK>(descL, maskL, descR, W, dmax, disp, v, tile * kMfmaTX);
 }
 
 // ===========================================================================
@@ -1377,46 +1396,53 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
   }
 }
 
+// Both describe stages of a batch in one persistent launch.  One workgroup
+// in `right_every` starts on the descriptor-only queue, the others on the
+// describe+mask queue, and each turns to the other queue when its own is
+// empty: the LDS-bound descriptor-only tiles and the issue-bound
+// describe+mask tiles share the CUs instead of following each other.
 template <int NW, int TW>
-__global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe_mask(
-    const BatchWork *__restrict__ bw, DescribeConsts c) {
-  extern __shared__ uint32_t tile[];
+__global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
+    const BatchWork *__restrict__ bw, DescribeConsts cm, RightConsts cr, int right_every) {
+  static_assert(kDescThreads == kRightThreads, "one workgroup shape for both stages");
+  extern __shared__ uint32_t dlds[];
   __shared__ int slot;
-  const int *start = bw->start + kQueueDescribeMask * (bw->npairs + 1);
-  const int total = start[bw->npairs];
-  for (;;) {
-    const int t = take(bw->counters + kQueueDescribeMask, &slot);
-    if (t >= total) break;
-    const int i = owner(start, bw->npairs, t);
-    const BatchPair &p = bw->pairs[bw->order[i]];
-    const int W = uniform(p.W), H = uniform(p.H);
-    const int tx = (W + TW - 1) / TW;
-    const int local = t - start[i];
-    describe_mask_tile<NW, TW, kDescTH>(tile, uniform(p.packedL), W, H, c, uniform(p.descL),
-                               uniform(p.maskL), (local % tx) * TW, (local / tx) * kDescTH);
-  }
-}
-
-// Descriptor-only tiles: the right view of every pair, plus the left view
-// when the mask is off.
-__global__ __launch_bounds__(kRightThreads) void k_batch_describe_right(
-    const BatchWork *__restrict__ bw, RightConsts c) {
-  extern __shared__ uint8_t rlds[];
-  __shared__ int slot;
-  const int *start = bw->start + kQueueDescribe * (bw->npairs + 1);
-  const int total = start[bw->npairs];
-  for (;;) {
-    const int t = take(bw->counters + kQueueDescribe, &slot);
-    if (t >= total) break;
-    const int i = owner(start, bw->npairs, t);
-    const BatchPair &p = bw->pairs[bw->order[i]];
-    const int W = uniform(p.W), H = uniform(p.H);
-    const int tx = (W + kRightTW - 1) / kRightTW, ty = (H + kRightTH - 1) / kRightTH;
-    const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
-    // view 0 is the right view; view 1 (mask off only) the left view
-    describe_right_tile<kRightPx>(rlds, uniform(view ? p.packedL : p.packedR), W, H, c,
-                        uniform(view ? p.descL : p.descR), (tile % tx) * kRightTW,
-                        (tile / tx) * kRightTH);
+  const int n = bw->npairs;
+  const bool right_first = blockIdx.x % right_every == 0;
+  for (int phase = 0; phase < 2; ++phase) {
+    if ((phase == 0) == right_first) {
+      const int *start = bw->start + kQueueDescribe * (n + 1);
+      const int total = start[n];
+      for (;;) {
+        const int t = take(bw->counters + kQueueDescribe, &slot);
+        if (t >= total) break;
+        const int i = owner(start, n, t);
+        const BatchPair &p = bw->pairs[bw->order[i]];
+        const int W = uniform(p.W), H = uniform(p.H);
+        const int tx = (W + kRightTW - 1) / kRightTW, ty = (H + kRightTH - 1) / kRightTH;
+        const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
+        // view 0 is the right view; view 1 (mask off only) the left view
+        describe_right_tile<kRightPx>(reinterpret_cast<uint8_t *>(dlds),
+                                      uniform(view ? p.packedL : p.packedR), W, H, cr,
+                                      uniform(view ? p.descL : p.descR), (tile % tx) * kRightTW,
+                                      (tile / tx) * kRightTH);
+      }
+    } else {
+      const int *start = bw->start + kQueueDescribeMask * (n + 1);
+      const int total = start[n];
+      for (;;) {
+        const int t = take(bw->counters + kQueueDescribeMask, &slot);
+        if (t >= total) break;
+        const int i = owner(start, n, t);
+        const BatchPair &p = bw->pairs[bw->order[i]];
+        const int W = uniform(p.W), H = uniform(p.H);
+        const int tx = (W + TW - 1) / TW;
+        const int local = t - start[i];
+        describe_mask_tile<NW, TW, kDescTH>(dlds, uniform(p.packedL), W, H, cm,
+                                            uniform(p.descL), uniform(p.maskL),
+                                            (local % tx) * TW, (local / tx) * kDescTH);
+      }
+    }
   }
 }
 
@@ -1460,6 +1486,38 @@ __global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restric
                                    p.cost, x + kXcds * (local / tiles),
                                    (local % tiles) * kCostTX);
       cur = next;
+    }
+  }
+}
+
+// The no-volume cost queues on the matrix cores: an item (a 128-pixel row
+// tile) goes to a workgroup of four waves, one 32-pixel tile each.
+template <int NW, bool MASK>
+__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
+    const BatchWork *__restrict__ bw) {
+  static_assert(kCostTX == kMfmaWaves * kMfmaTX, "an item is one tile per wave");
+  __shared__ int slot;
+  const int wave = threadIdx.x >> 6;
+  const int home = blockIdx.x % kXcds;
+  const int n = bw->npairs;
+  for (int qi = 0; qi < kXcds; ++qi) {
+    const int x = (home + qi) % kXcds;
+    const int q = kQueueCost0 + x;
+    const int *start = bw->start + q * (n + 1);
+    const int total = start[n];
+    for (;;) {
+      const int cur = take(bw->counters + q, &slot);
+      if (cur >= total) break;
+      const int i = owner(start, n, cur);
+      const BatchPair &p = bw->pairs[bw->order[i]];
+      const int W = uniform(p.W);
+      const int tiles = (W + kCostTX - 1) / kCostTX;
+      const int local = cur - start[i];
+      const int v = x + kXcds * (local / tiles);
+      const int u0 = (local % tiles) * kCostTX + wave * kMfmaTX;
+      if (u0 < W)
+        cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
+                                 uniform(p.dmax), uniform(p.disp), v, u0);
     }
   }
 }
@@ -1580,22 +1638,20 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
   const int g0 = persistent_grid(k_batch_color, kColorThreads, 0, tu.blocks_per_cu[0]);
   hipLaunchKernelGGL(k_batch_color, dim3(g0), dim3(kColorThreads), 0, s, bw, t.lin, t.f,
                      t.mq, use_mask);
-  if (use_mask) {
-    DescribeConsts c = describe_consts(t);
-    c.pitch = t.left_pitch_for(TW);
-    const size_t lds = mask_lds_bytes(t, TW);
-    const int g1 = persistent_grid(k_batch_describe_mask<NW, TW>, kDescThreads, lds,
-                                   tu.blocks_per_cu[1]);
-    hipLaunchKernelGGL((k_batch_describe_mask<NW, TW>), dim3(g1), dim3(kDescThreads), lds, s,
-                       bw, c);
-  }
   {
-    static const hipError_t attr = allow_big_lds(reinterpret_cast<const void *>(k_batch_describe_right));
+    // both describe stages (the describe+mask queue is empty without a mask)
+    static const hipError_t attr =
+        allow_big_lds(reinterpret_cast<const void *>(k_batch_describe<NW, TW>));
     if (attr != hipSuccess) return attr;
-    const size_t lds = right_lds_bytes(kRightPx, t.radius, t.right_pitch);
-    const int g2 = persistent_grid(k_batch_describe_right, kRightThreads, lds, tu.blocks_per_cu[2]);
-    hipLaunchKernelGGL(k_batch_describe_right, dim3(g2), dim3(kRightThreads), lds, s, bw,
-                       right_consts(t));
+    DescribeConsts cm = describe_consts(t);
+    cm.pitch = t.left_pitch_for(TW);
+    const size_t lds = std::max(mask_lds_bytes(t, TW), right_lds_bytes(kRightPx, t.radius,
+                                                                        t.right_pitch));
+    const int g1 = persistent_grid(k_batch_describe<NW, TW>, kDescThreads, lds,
+                                   tu.blocks_per_cu[1]);
+    const int right_every = tu.blocks_per_cu[2] > 0 ? tu.blocks_per_cu[2] : kDescRightEvery;
+    hipLaunchKernelGGL((k_batch_describe<NW, TW>), dim3(g1), dim3(kDescThreads), lds, s, bw, cm,
+                       right_consts(t), use_mask ? right_every : 1);
   }
   {
     // pairs without a volume, then pairs with one (each kernel's queues are
@@ -1606,14 +1662,23 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
     const int g3 = persistent_grid(k_batch_cost<NW, DC, M, V>, 64, lds, tu.blocks_per_cu[3]); \
     hipLaunchKernelGGL((k_batch_cost<NW, DC, M, V>), dim3(g3), dim3(64), lds, s, bw);        \
   } while (0)
+#define BSM_LAUNCH_BATCH_COST_MFMA(M)                                                          \
+  do {                                                                                        \
+    const int g3 = persistent_grid(k_batch_cost_mfma<NW, M>, 64 * kMfmaWaves, 0,            \
+                                   tu.blocks_per_cu[3]);                                        \
+    hipLaunchKernelGGL((k_batch_cost_mfma<NW, M>), dim3(g3), dim3(64 * kMfmaWaves), 0, s, bw); \
+  } while (0)
     if (use_mask) {
-      BSM_LAUNCH_BATCH_COST(true, false);
+      if (tu.cost_mfma) BSM_LAUNCH_BATCH_COST_MFMA(true);
+      else BSM_LAUNCH_BATCH_COST(true, false);
       BSM_LAUNCH_BATCH_COST(true, true);
     } else {
-      BSM_LAUNCH_BATCH_COST(false, false);
+      if (tu.cost_mfma) BSM_LAUNCH_BATCH_COST_MFMA(false);
+      else BSM_LAUNCH_BATCH_COST(false, false);
       BSM_LAUNCH_BATCH_COST(false, true);
     }
 #undef BSM_LAUNCH_BATCH_COST
+#undef BSM_LAUNCH_BATCH_COST_MFMA
   }
   return hipGetLastError();
 }

@@ -151,35 +151,53 @@ def test_batch_equals_single_pair_path_full_size(torch_cuda, bsm, orc):
     ctx.close()
 
 
-TUNINGS = [dict(desc_tile_w=tw, cost_dchunk=dc, blocks_per_cu=[0, bm, 0, bc])
-           for tw in (16, 32) for dc in (32, 64) for bm, bc in ((0, 0), (2, 1))]
+TUNINGS = [dict(desc_tile_w=tw, cost_dchunk=dc, blocks_per_cu=[0, bm, 0, bc], cost_mfma=mf)
+           for tw in (16, 32) for dc in (32, 64) for bm, bc in ((0, 0), (2, 1)) for mf in (1, 0)
+           if mf == 1 or (bm, bc) == (0, 0)]
+_TUNING_SCENE = {}
+
+
+def _tuning_scene(orc, pat):
+    key = pat.tobytes()
+    if key not in _TUNING_SCENE:
+        sc = synth.slanted_scene(33, 300, 70, 130)
+        _TUNING_SCENE[key] = sc, orc.match(sc.left, sc.right, pat, sc.dmax, want_cost=True)
+    return _TUNING_SCENE[key]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"tw{t['desc_tile_w']}-dc{t['cost_dchunk']}-"
-                         f"b{t['blocks_per_cu'][1]}{t['blocks_per_cu'][3]}")
+                         f"b{t['blocks_per_cu'][1]}{t['blocks_per_cu'][3]}-mfma{t['cost_mfma']}")
 def test_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
+    # single pair with and without a volume, and a persistent two-pair batch
+    # with and without volumes, under each launch choice
     torch = torch_cuda
     _say(f"case: tuning {tuning}")
     ctx, pat = _ctx(bsm, orc, 1024, 31, seed=11)
-    sc = synth.slanted_scene(33, 300, 70, 130)
+    sc, (wd, wc) = _tuning_scene(orc, pat)
     ctx.set_tuning(tuning)
     assert ctx.tuning() == tuning
     L, R = _dev(torch, sc.left), _dev(torch, sc.right)
     disp, cost = ctx.match(L, R, sc.dmax, want_cost=True)
-    outs = ctx.match_batch([(L, R, sc.dmax)], want_cost=True)
+    disp_nv, _ = ctx.match(L, R, sc.dmax, want_cost=False)
+    outs = ctx.match_batch([(L, R, sc.dmax)] * 2, want_cost=False)
+    outs_v = ctx.match_batch([(L, R, sc.dmax)] * 2, want_cost=True)
     torch.cuda.synchronize()
-    wd, wc = orc.match(sc.left, sc.right, pat, sc.dmax, want_cost=True)
     assert np.array_equal(disp.cpu().numpy(), wd)
     assert np.array_equal(cost.cpu().numpy(), wc)
-    assert np.array_equal(outs[0][0].cpu().numpy(), wd)
-    assert np.array_equal(outs[0][1].cpu().numpy(), wc)
+    assert np.array_equal(disp_nv.cpu().numpy(), wd)
+    for o in outs:
+        assert np.array_equal(o[0].cpu().numpy(), wd)
+    for o in outs_v:
+        assert np.array_equal(o[0].cpu().numpy(), wd)
+        assert np.array_equal(o[1].cpu().numpy(), wc)
     ctx.close()
 
 
 def test_set_tuning_validates(torch_cuda, bsm, orc):
     ctx, _ = _ctx(bsm, orc, 256, 15)
     for bad in (dict(desc_tile_w=8, cost_dchunk=64), dict(desc_tile_w=16, cost_dchunk=48),
-                dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 65])):
+                dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 65]),
+                dict(desc_tile_w=16, cost_dchunk=64, cost_mfma=2)):
         assert bsm.bsm_set_tuning(ctx.h, bsm.Tuning.from_dict(bad)) == bsm.EINVAL
     ctx.close()
 
