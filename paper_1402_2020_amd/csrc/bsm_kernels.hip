@@ -893,8 +893,10 @@ __global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restr
 // 32-bit slice, one byte per bit, for left pixel u0 + c (A operand, kept in
 // registers for the whole tile) and right pixel r0 + c (B operand, expanded
 // from the packed words at each step).  Which bit sits in which byte is free
-// as long as A and B agree: byte r of dword q holds bit 8r + 4h + q, so dword
-// q of B is ((x >> 4h) >> q) & 0x01010101, two operations.  Right block q
+// as long as A and B agree: byte r of dword q holds bit 8r + 4h + q.  B keeps
+// that bit where it is, (x >> 4h) & (0x01010101 << q) (byte value 2^q, one
+// AND per dword), and A carries v (8 >> q), so every product is 8 v b and
+// the accumulator, started at 8n, ranks 8 (n + sum v b).  Right block q
 // holds the pixels u0 - 32q + j, so entry (i, j) is disparity 32q + i - j and
 // the blocks q = 0 .. Q-1 cover [0, dmax).  The accumulator gives lane (c, h)
 // row 8(e/4) + 4h + e%4 of column c in its element e; the lane keeps the
@@ -931,10 +933,9 @@ __device__ __forceinline__ void load_slices(const uint64_t *p, uint32_t *out) {
   }
 }
 
-// Bits q, q + 8, q + 16, q + 24 of y as the four bytes of a dword (0 or 1);
-// `ones` = 0x01010101, or 0 to give zeros.
-__device__ __forceinline__ uint32_t byte_bits(uint32_t y, int q, uint32_t ones = 0x01010101u) {
-  return (y >> q) & ones;
+// Bits q, q + 8, q + 16, q + 24 of y as the four bytes of a dword (0 or 1).
+__device__ __forceinline__ uint32_t byte_bits(uint32_t y, int q) {
+  return (y >> q) & 0x01010101u;
 }
 
 // One wave: the 32 left pixels of row v from u0.
@@ -965,13 +966,14 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
       if (!MASK) mw[s] = 0xffffffffu;
       if (!has_a) aw[s] = mw[s] = 0;
       const uint32_t x = aw[s] & mw[s];
-      // bytes 1 for (m, !a), 0xff for (m, a), 0 for !m: pos + 255 neg, where
-      // 255 neg = (neg << 8) - neg has no carries (each byte of neg is 0 or 1)
+      // bytes +w for (m, !a), -w for (m, a), 0 for !m, w = 8 >> q: the B
+      // byte of the same bit holds 2^q (see below), so every product is 8 v b.
+      // As integers, pos << k + neg (256 - w) with k = 3 - q; no byte carries.
       const uint32_t py = (mw[s] & ~aw[s]) >> (4 * h), ny = x >> (4 * h);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t pos = byte_bits(py, q), neg = byte_bits(ny, q);
-        A[s][q] = static_cast<int>((neg << 8) + pos - neg);
+        A[s][q] = static_cast<int>((pos << (3 - q)) + (neg << 8) - (neg << (3 - q)));
       }
     }
   }
@@ -986,16 +988,21 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
   load_slices<NW>(rowR + (size_t)right_px(0) * NW, bw);
   for (int q = 0; q < nq; ++q) {
     const int rb = u0 - kMfmaTX * q + c;  // the lane's right pixel
-    const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;  // missing pixel: B = 0
+    // B dword q4 keeps bits q4 + 8r of the shifted word in place (byte
+    // value 2^q4), one AND each; a missing right pixel gives B = 0.
+    const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;
+    uint32_t bmask[4];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) bmask[q4] = ones << q4;
     v16i32 acc;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 64 * NW;  // n + sum v b >= 0
+    for (int e = 0; e < 16; ++e) acc[e] = 8 * 64 * NW;  // 8 (n + sum v b) >= 0
 #pragma unroll
     for (int s = 0; s < kSlices; ++s) {
       const uint32_t by = bw[s] >> (4 * h);
       v4i32 B;
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(byte_bits(by, q4, ones));
+      for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(by & bmask[q4]);
       acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc, 0, 0, 0);
     }
     // the next block's words load while this block's products finish
