@@ -244,10 +244,11 @@ typedef struct {
                                  (0 = as many as fit, max 64); [2]: one
                                  describe workgroup in this many starts on
                                  the descriptor-only tiles (0 = 4)          */
-    int32_t cost_mfma;        /* 1 (default): cost + WTA without a volume on
-                                 the matrix cores (the cost as an integer
-                                 dot product); 0: the bitwise VALU kernel.
-                                 Calls with a volume always take the latter */
+    int32_t cost_mfma;        /* 1 (default): cost + WTA on the matrix cores
+                                 (the cost as an integer dot product) for
+                                 n <= 1024 and 16 < dmax (<= 256 with a
+                                 volume; single pairs, and batch pairs
+                                 without one); 0: the bitwise VALU kernel */
 } bsm_tuning;
 
 bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out);

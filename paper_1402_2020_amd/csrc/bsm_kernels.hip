@@ -938,16 +938,24 @@ __device__ __forceinline__ uint32_t byte_bits(uint32_t y, int q) {
   return (y >> q) & 0x01010101u;
 }
 
-// One wave: the 32 left pixels of row v from u0.
-template <int NW, bool MASK>
+// Largest dmax of the matrix-core kernel with a volume: the wave's slab of
+// the volume (dmax x 32 costs) is assembled in LDS.
+constexpr int kMfmaVolMaxD = 256;
+
+// One wave: the 32 left pixels of row v from u0.  With VOL, `slab` is the
+// wave's LDS (dmax x 32 int16): each cost goes there first, at [d][i], and
+// the slab leaves as whole 64-byte rows of cost[d][v][u0 .. u0 + 31].
+template <int NW, bool MASK, bool VOL = false>
 __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ descL,
                                                const uint64_t *__restrict__ maskL,
                                                const uint64_t *__restrict__ descR, int W,
-                                               int dmax, int32_t *__restrict__ disp, int v,
+                                               int H, int dmax, int32_t *__restrict__ disp,
+                                               int16_t *__restrict__ cost, int16_t *slab, int v,
                                                int u0) {
   constexpr int kSlices = 2 * NW;  // 32-bit slices of a string
   const int lane = threadIdx.x & 63;
   const int c = lane & 31, h = lane >> 5;
+  int am = 0;  // popcount(a & m) of the lane's left pixel (volume only)
 
   // A operands of the lane's left pixel.  Loads
   // are unconditional from a clamped pixel (16 bytes at a time; every
@@ -966,6 +974,7 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
       if (!MASK) mw[s] = 0xffffffffu;
       if (!has_a) aw[s] = mw[s] = 0;
       const uint32_t x = aw[s] & mw[s];
+      if (VOL) am += __builtin_popcount(x);
       // bytes +w for (m, !a), -w for (m, a), 0 for !m, w = 8 >> q: the B
       // byte of the same bit holds 2^q (see below), so every product is 8 v b.
       // As integers, pos << k + neg (256 - w) with k = 3 - q; no byte carries.
@@ -976,6 +985,12 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
         A[s][q] = static_cast<int>((pos << (3 - q)) + (neg << 8) - (neg << (3 - q)));
       }
     }
+  }
+  // costs: C = popcount(a & m) + sum v b = am_row + acc / 8 - n
+  int cbase[16];
+  if (VOL) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) cbase[e] = __shfl(am, 8 * (e / 4) + 4 * h + (e % 4)) - 64 * NW;
   }
   uint32_t best[16];
 #pragma unroll
@@ -1011,6 +1026,15 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
     // right pixel exists (u - d = rb >= 0).  Blocks whose every entry is
     // valid (the wave-uniform test below) skip the per-element checks.
     const int dbase = kMfmaTX * q - c;
+    if (VOL) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
+        if (d >= 0 && d < dmax)
+          slab[d * kMfmaTX + 8 * (e / 4) + 4 * h + (e % 4)] = static_cast<int16_t>(
+              rb >= 0 ? cbase[e] + (acc[e] >> 3) : kInvalidCost);
+      }
+    }
     if (q >= 1 && kMfmaTX * q + kMfmaTX - 1 < dmax && u0 - kMfmaTX * q >= 0) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -1041,6 +1065,25 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
     const int u = u0 + 8 * (c / 4) + 4 * h + (c % 4);
     if (u < W) disp[(size_t)v * W + u] = static_cast<int32_t>(key & 0xffffu);
   }
+  if (VOL) {
+    // The slab was written by the lanes of this wave only; LDS accesses of
+    // one wave are performed in order, so a wave-level fence suffices.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // four rows per pass: lane l takes row 4k + l / 16, pixels 2 (l % 16), + 1
+    const int pr = lane >> 4, px = 2 * (lane & 15), u = u0 + px;
+    for (int d = pr; d < dmax; d += 4) {
+      const uint32_t two = *reinterpret_cast<const uint32_t *>(slab + d * kMfmaTX + px);
+      int16_t *dst = cost + ((size_t)d * H + v) * W + u;
+      if (u + 1 < W && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
+        *reinterpret_cast<uint32_t *>(dst) = two;
+      } else {
+        if (u < W) dst[0] = static_cast<int16_t>(two & 0xffffu);
+        if (u + 1 < W) dst[1] = static_cast<int16_t>(two >> 16);
+      }
+    }
+  }
 }
 
 template <int NW, bool MASK>
@@ -1054,7 +1097,26 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
   const int v = xcd + kXcds * (slot / groups);
   const int tile = (slot % groups) * kMfmaWaves + (threadIdx.x >> 6);
   if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
-  cost_tile_mfma<NW, MASK>(descL, maskL, descR, W, dmax, disp, v, tile * kMfmaTX);
+  cost_tile_mfma<NW, MASK>(descL, maskL, descR, W, H, dmax, disp, nullptr, nullptr, v,
+                           tile * kMfmaTX);
+}
+
+// With the volume (dmax <= kMfmaVolMaxD): dynamic LDS of kMfmaWaves slabs.
+template <int NW, bool MASK>
+__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
+    const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
+    const uint64_t *__restrict__ descR, int W, int H, int dmax, int32_t *__restrict__ disp,
+    int16_t *__restrict__ cost) {
+  extern __shared__ int16_t slabs[];
+  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
+  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / groups);
+  const int wave = threadIdx.x >> 6;
+  const int tile = (slot % groups) * kMfmaWaves + wave;
+  if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
+  cost_tile_mfma<NW, MASK, true>(descL, maskL, descR, W, H, dmax, disp, cost,
+                                 slabs + (size_t)wave * dmax * kMfmaTX, v, tile * kMfmaTX);
 }
 
 // ===========================================================================
@@ -1524,7 +1586,8 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
       const int u0 = (local % tiles) * kCostTX + wave * kMfmaTX;
       if (u0 < W)
         cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
-                                 uniform(p.dmax), uniform(p.disp), v, u0);
+                                 uniform(p.H), uniform(p.dmax), uniform(p.disp), nullptr,
+                                 nullptr, v, u0);
     }
   }
 }
@@ -1600,10 +1663,25 @@ hipError_t launch_cost_fast_dc(const uint64_t *descL, const uint64_t *maskL,
 
 template <int NW>
 hipError_t launch_cost_mfma(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
-                            int W, int H, int dmax, int32_t *disp, hipStream_t s) {
+                            int W, int H, int dmax, int32_t *disp, int16_t *cost, hipStream_t s) {
   const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
   const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
   dim3 grid(kXcds * groups * ((H + kXcds - 1) / kXcds));
+  if (cost) {
+    static const hipError_t attr[2] = {
+        allow_big_lds(reinterpret_cast<const void *>(k_cost_wta_mfma_vol<NW, false>)),
+        allow_big_lds(reinterpret_cast<const void *>(k_cost_wta_mfma_vol<NW, true>))};
+    if (attr[0] != hipSuccess) return attr[0];
+    if (attr[1] != hipSuccess) return attr[1];
+    const size_t lds = (size_t)kMfmaWaves * dmax * kMfmaTX * sizeof(int16_t);
+    if (maskL)
+      hipLaunchKernelGGL((k_cost_wta_mfma_vol<NW, true>), grid, dim3(64 * kMfmaWaves), lds, s,
+                         descL, maskL, descR, W, H, dmax, disp, cost);
+    else
+      hipLaunchKernelGGL((k_cost_wta_mfma_vol<NW, false>), grid, dim3(64 * kMfmaWaves), lds, s,
+                         descL, maskL, descR, W, H, dmax, disp, cost);
+    return hipGetLastError();
+  }
   if (maskL)
     hipLaunchKernelGGL((k_cost_wta_mfma<NW, true>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
                        maskL, descR, W, H, dmax, disp);
@@ -1808,13 +1886,15 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const u
                            int W, int H, int nw, int dmax, int32_t *disp, int16_t *cost,
                            const DeviceTables &t, hipStream_t s) {
   const int dc = t.tune.cost_dchunk;
-  if (!cost && t.tune.cost_mfma) {  // matrix-core kernel (no volume)
+  // Matrix-core kernel, except for short disparity ranges (a tile computes
+  // at least two 32-wide blocks, most of them wasted when dmax <= 16).
+  if (t.tune.cost_mfma && dmax > 16 && (!cost || dmax <= kMfmaVolMaxD)) {
     switch (nw) {
-      case 1: return launch_cost_mfma<1>(descL, maskL, descR, W, H, dmax, disp, s);
-      case 2: return launch_cost_mfma<2>(descL, maskL, descR, W, H, dmax, disp, s);
-      case 4: return launch_cost_mfma<4>(descL, maskL, descR, W, H, dmax, disp, s);
-      case 8: return launch_cost_mfma<8>(descL, maskL, descR, W, H, dmax, disp, s);
-      case 16: return launch_cost_mfma<16>(descL, maskL, descR, W, H, dmax, disp, s);
+      case 1: return launch_cost_mfma<1>(descL, maskL, descR, W, H, dmax, disp, cost, s);
+      case 2: return launch_cost_mfma<2>(descL, maskL, descR, W, H, dmax, disp, cost, s);
+      case 4: return launch_cost_mfma<4>(descL, maskL, descR, W, H, dmax, disp, cost, s);
+      case 8: return launch_cost_mfma<8>(descL, maskL, descR, W, H, dmax, disp, cost, s);
+      case 16: return launch_cost_mfma<16>(descL, maskL, descR, W, H, dmax, disp, cost, s);
       default: break;
     }
   }

@@ -182,16 +182,18 @@ MFMA_CASES = [
     (257, 2, 16, 130, False),
     (64, 4, 16, 64, True),
     (450, 2, 16, 60, True),
+    (259, 3, 16, 256, True),   # largest dmax with the volume on the matrix cores, odd W
+    (77, 3, 4, 40, False),     # odd W, Eq. 4
 ]
 
 
 @pytest.mark.parametrize("W,H,nw,dmax,use_mask", MFMA_CASES)
 def test_cost_wta_matrix_core_and_bitwise(torch_cuda, bsm, orc, W, H, nw, dmax, use_mask):
-    # without a volume the fused cost + WTA runs on the matrix cores by
-    # default (the cost as an integer dot product); both kernels must give
-    # the oracle's winners
+    # the fused cost + WTA runs on the matrix cores by default (the cost as
+    # an integer dot product; with a volume up to dmax 256); both kernels
+    # must give the oracle's winners and volume
     torch = torch_cuda
-    _say(f"case: cost_wta no volume, mfma and bitwise, W={W} H={H} nw={nw} dmax={dmax} "
+    _say(f"case: cost_wta mfma and bitwise, with and without volume, W={W} H={H} nw={nw} dmax={dmax} "
          f"mask={use_mask}")
     rng = np.random.Generator(np.random.PCG64(7 * W + H + 13 * nw + dmax))
     base = rng.integers(0, 2**63, (H, W + dmax, nw), dtype=np.uint64)
@@ -201,7 +203,8 @@ def test_cost_wta_matrix_core_and_bitwise(torch_cuda, bsm, orc, W, H, nw, dmax, 
     dr = np.ascontiguousarray(base[:, dmax:dmax + W])
     dl = np.ascontiguousarray(base[:, dmax - shift:dmax - shift + W] ^ noise)
     m = rng.integers(0, 2**63, (H, W, nw), dtype=np.uint64) if use_mask else None
-    want = orc.wta(orc.cost_volume(dl, m, dr, dmax))
+    want_cost = orc.cost_volume(dl, m, dr, dmax)
+    want = orc.wta(want_cost)
     ctx, _ = _ctx(bsm, orc, 64 * nw, 3)
     t = lambda a: None if a is None else _dev(torch, a.view(np.int64))
     for mfma in (1, 0):
@@ -209,8 +212,11 @@ def test_cost_wta_matrix_core_and_bitwise(torch_cuda, bsm, orc, W, H, nw, dmax, 
         tune["cost_mfma"] = mfma
         ctx.set_tuning(tune)
         disp, _ = ctx.cost_wta(t(dl), t(m), t(dr), dmax, want_cost=False)
+        disp_v, cost = ctx.cost_wta(t(dl), t(m), t(dr), dmax, want_cost=True)
         torch.cuda.synchronize()
         assert np.array_equal(disp.cpu().numpy(), want), mfma
+        assert np.array_equal(disp_v.cpu().numpy(), want), mfma
+        assert np.array_equal(cost.cpu().numpy(), want_cost), mfma
     ctx.close()
 
 
