@@ -26,6 +26,13 @@ sys.path.insert(0, ROOT)
 CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
 ALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ          # 3.93e13 lane-ops/s
 HBM_PEAK_BPS = 8.0e12
+MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix ops/s
+
+
+def cost_on_matrix_cores(tuning, n, dmax, want_cost):
+    """Whether bsm_cost_wta takes the matrix-core kernel (the library's rule)."""
+    return (tuning.get("cost_mfma", 1) == 1 and n // 64 in (1, 2, 4, 8, 16) and dmax > 16
+            and (not want_cost or dmax <= 256))
 
 WORKLOADS = {
     0: "128x96 rectangles, dmax 16, n 256, S 15",
@@ -582,11 +589,18 @@ def main():
         "describe_right": npx * 1 * n,          # per pair: tau
         "cost_wta": evals * (n // 16 + 1),      # per eval: n/32 x (bitop3 + bcnt) + min
     }
+    # On the matrix cores an evaluation is an n-term int8 dot product (2n
+    # ops); the bitwise count above stays as the VALU-popcount equivalent.
+    mfma = cost_on_matrix_cores(ctx.tuning(), n, dmax, p["want_cost"])
     bytes_ = {"color_left": npx * 7, "color_right": npx * 7}
     kernels = {}
     for name, ms in kern_ms.items():
         ent = {"ms": round(ms, 5)}
-        if name in ops:
+        if name == "cost_wta" and mfma:
+            ent.update(bound="mfma", achieved_Tops=evals * 2 * n / (ms / 1e3) / 1e12,
+                       frac=evals * 2 * n / (ms / 1e3) / MFMA_I8_PEAK_OPS,
+                       valu_popcount_equiv_frac=ops[name] / (ms / 1e3) / ALU_PEAK_OPS)
+        elif name in ops:
             ent.update(bound="alu", achieved_Tops=ops[name] / (ms / 1e3) / 1e12,
                        frac=ops[name] / (ms / 1e3) / ALU_PEAK_OPS)
         else:
@@ -595,7 +609,13 @@ def main():
         kernels[name] = ent
     dom = max(kern_ms, key=kern_ms.get)
     dms = kern_ms[dom]
-    if dom in ops:
+    if dom == "cost_wta" and mfma:
+        achieved = evals * 2 * n / (dms / 1e3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
+                "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s",
+                "frac": round(achieved * 1e12 / MFMA_I8_PEAK_OPS, 4),
+                "traffic": traffic_for(dom, cfg)}
+    elif dom in ops:
         achieved = ops[dom] / (dms / 1e3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(ALU_PEAK_OPS / 1e12, 2), "unit": "TOP/s",
