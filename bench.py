@@ -322,10 +322,16 @@ def bench_nsweep(args):
         torch.cuda.synchronize()
         ms_cost = e0.elapsed_time(e1) / steps
         evals = W * H * dmax
+        on_mfma = cost_on_matrix_cores(ctx.tuning(), n, dmax, False)
         rows.append({"n_bits": n, "ms_per_pair": round(ms, 4), "evals_per_s": evals / (ms / 1e3),
                      "ms_describe_both_views": round(ms_desc, 4), "ms_cost_wta": round(ms_cost, 4),
-                     "cost_wta_frac_of_alu_peak": evals * (n / 16 + 1) / (ms_cost / 1e3) /
-                     ALU_PEAK_OPS})
+                     "cost_wta_kernel": "mfma" if on_mfma else "valu",
+                     # the bitwise op count (n/16 + 1 per evaluation) against the
+                     # VALU peak; above 1 when the matrix cores beat that roofline
+                     "cost_wta_valu_popcount_equiv_frac": evals * (n / 16 + 1) / (ms_cost / 1e3) /
+                     ALU_PEAK_OPS,
+                     "cost_wta_frac_of_mfma_i8_peak": (evals * 2 * n / (ms_cost / 1e3) /
+                                                       MFMA_I8_PEAK_OPS) if on_mfma else None})
         print(json.dumps({"progress": "nsweep", **rows[-1]}), flush=True)
         ctx.close()
     # least-squares slope of time against n (the paper states linear cost in n)
