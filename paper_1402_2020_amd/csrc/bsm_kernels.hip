@@ -22,9 +22,10 @@ constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
 // ===========================================================================
 // Colour pre-pass.  Output uint32 per pixel: byte 0 L8, byte 1 a8, byte 2 b8,
-// byte 3 intensity I.  Tiles of 64 x 16 pixels: 256 threads, 4 rows each.
+// byte 3 intensity I.  Tiles of 64 x 4 pixels, one pixel per thread (small
+// tiles: even a 128 x 96 view gets 48 workgroups).
 // ===========================================================================
-constexpr int kColorTX = 64, kColorTY = 16, kColorThreads = 256;
+constexpr int kColorTX = 64, kColorTY = 4, kColorThreads = 256;
 constexpr int kColorRowsPerThread = kColorTX * kColorTY / kColorThreads;
 
 // floor((2a + b) / (2b)) for b > 0: a / b rounded to nearest, halves up.
