@@ -22,11 +22,14 @@ constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
 // ===========================================================================
 // Colour pre-pass.  Output uint32 per pixel: byte 0 L8, byte 1 a8, byte 2 b8,
-// byte 3 intensity I.  Tiles of 64 x 4 pixels, one pixel per thread (small
-// tiles: even a 128 x 96 view gets 48 workgroups).
+// byte 3 intensity I.  Tiles of 64 x (4 RPT) pixels, RPT rows per thread:
+// one for the single-pair kernel (even a 128 x 96 view gets 48 workgroups),
+// eight for the persistent batch kernel (fewer queue pulls).
 // ===========================================================================
-constexpr int kColorTX = 64, kColorTY = 4, kColorThreads = 256;
-constexpr int kColorRowsPerThread = kColorTX * kColorTY / kColorThreads;
+constexpr int kColorTX = 64, kColorThreads = 256;
+constexpr int kColorRows = kColorThreads / kColorTX;     // rows per pass
+constexpr int kColorRPT = 1, kBatchColorRPT = 8;        // passes per tile
+constexpr int kColorTY = kColorRows * kColorRPT, kBatchColorTY = kColorRows * kBatchColorRPT;
 
 // floor((2a + b) / (2b)) for b > 0: a / b rounded to nearest, halves up.
 __device__ __forceinline__ int32_t nearest_div(int64_t a, int64_t b) {
@@ -42,6 +45,7 @@ __device__ __forceinline__ uint32_t clamp_u8(int32_t x) {
 
 // mirror != 0 writes pixel u of a row to column W - 1 - u (the horizontally
 // mirrored view, used for right-reference matching).
+template <int RPT>
 __device__ __forceinline__ void color_tile(const uint8_t *__restrict__ img, int W, int H,
                                            int stride, uint32_t *__restrict__ out,
                                            const uint16_t *__restrict__ lin,
@@ -50,8 +54,8 @@ __device__ __forceinline__ void color_tile(const uint8_t *__restrict__ img, int 
   const int u = u0 + (threadIdx.x % kColorTX);
   if (u >= W) return;
 #pragma unroll
-  for (int r = 0; r < kColorRowsPerThread; ++r) {
-    const int v = v0 + r * (kColorThreads / kColorTX) + (threadIdx.x / kColorTX);
+  for (int r = 0; r < RPT; ++r) {
+    const int v = v0 + r * kColorRows + (threadIdx.x / kColorTX);
     if (v >= H) return;
     const uint8_t *px = img + (size_t)v * stride + 3 * (size_t)u;
     const int32_t R = px[0], G = px[1], B = px[2];
@@ -77,8 +81,8 @@ __global__ __launch_bounds__(kColorThreads) void k_color(const uint8_t *__restri
                                                          const uint16_t *__restrict__ lin,
                                                          const uint16_t *__restrict__ ftab, Mq mq,
                                                          int want_lab, int mirror) {
-  color_tile(img, W, H, stride, out, lin, ftab, mq, want_lab, mirror, blockIdx.x * kColorTX,
-             blockIdx.y * kColorTY);
+  color_tile<kColorRPT>(img, W, H, stride, out, lin, ftab, mq, want_lab, mirror,
+                        blockIdx.x * kColorTX, blockIdx.y * kColorTY);
 }
 
 // Reverses every row of a [rows][W] array in place (maps results of the
@@ -1458,11 +1462,13 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
     if (t >= total) break;
     const int i = owner(start, bw->npairs, t);
     const BatchPair &p = bw->pairs[bw->order[i]];
-    const int tx = (p.W + kColorTX - 1) / kColorTX, ty = (p.H + kColorTY - 1) / kColorTY;
+    const int tx = (p.W + kColorTX - 1) / kColorTX;
+    const int ty = (p.H + kBatchColorTY - 1) / kBatchColorTY;
     const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
-    color_tile(view ? p.right : p.left, p.W, p.H, p.stride, view ? p.packedR : p.packedL, lin,
-               ftab, mq, view == 0 && use_mask, 0, (tile % tx) * kColorTX,
-               (tile / tx) * kColorTY);
+    color_tile<kBatchColorRPT>(view ? p.right : p.left, p.W, p.H, p.stride,
+                               view ? p.packedR : p.packedL, lin, ftab, mq,
+                               view == 0 && use_mask, 0, (tile % tx) * kColorTX,
+                               (tile / tx) * kBatchColorTY);
   }
 }
 
@@ -1794,7 +1800,8 @@ int describe_right_cols(int radius) {
 
 void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
                        int counts[kBatchQueues]) {
-  counts[kQueueColor] = 2 * ((W + kColorTX - 1) / kColorTX) * ((H + kColorTY - 1) / kColorTY);
+  counts[kQueueColor] =
+      2 * ((W + kColorTX - 1) / kColorTX) * ((H + kBatchColorTY - 1) / kBatchColorTY);
   counts[kQueueDescribeMask] =
       use_mask ? ((W + desc_tile_w - 1) / desc_tile_w) * ((H + kDescTH - 1) / kDescTH) : 0;
   counts[kQueueDescribe] =
