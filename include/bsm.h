@@ -49,6 +49,12 @@
  *            message for the calling thread's last failure.
  * Threads    A context may be used from one thread at a time, except
  *            bsm_submit / bsm_poll / bsm_drain, which lock internally.
+ * Streams    Device calls are ordered on the stream they are given.  The
+ *            single-pair calls (bsm_color / bsm_describe / bsm_match /
+ *            bsm_match_right / bsm_vote_refine) share context scratch: a
+ *            call on a different stream than the previous such call first
+ *            waits for the device to be idle, so one stream per context is
+ *            the fast way to use them.
  */
 #ifndef BSM_H
 #define BSM_H

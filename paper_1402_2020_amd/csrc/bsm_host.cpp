@@ -230,23 +230,26 @@ int choose_left_pitch(const int8_t *pattern, int n, int cols) {
 
 // ---------------------------------------------------------------------------
 Scratch::~Scratch() {
-  if (ev_) {
-    if (used_) (void)hipEventSynchronize(ev_);
-    (void)hipEventDestroy(ev_);
-  }
+  if (used_) (void)wait_last_use();
+  if (ev_) (void)hipEventDestroy(ev_);
   if (ptr_) (void)hipFree(ptr_);
+}
+
+hipError_t Scratch::wait_last_use() {
+  return tracked_ ? hipEventSynchronize(ev_) : hipDeviceSynchronize();
 }
 
 void *Scratch::acquire(size_t bytes, hipStream_t s, hipError_t *err) {
   *err = hipSuccess;
-  if (!ev_) {
+  if (tracked_ && !ev_) {
     *err = hipEventCreateWithFlags(&ev_, hipEventDisableTiming);
     if (*err != hipSuccess) return nullptr;
   }
   if (bytes > cap_) {
     if (used_) {
-      *err = hipEventSynchronize(ev_);
+      *err = wait_last_use();
       if (*err != hipSuccess) return nullptr;
+      used_ = false;
     }
     if (ptr_) (void)hipFree(ptr_);
     ptr_ = nullptr;
@@ -258,7 +261,7 @@ void *Scratch::acquire(size_t bytes, hipStream_t s, hipError_t *err) {
     }
     cap_ = bytes;
   } else if (used_ && last_ != s) {
-    *err = hipStreamWaitEvent(s, ev_, 0);
+    *err = tracked_ ? hipStreamWaitEvent(s, ev_, 0) : hipDeviceSynchronize();
     if (*err != hipSuccess) return nullptr;
   }
   return ptr_;
@@ -267,7 +270,7 @@ void *Scratch::acquire(size_t bytes, hipStream_t s, hipError_t *err) {
 hipError_t Scratch::release(hipStream_t s) {
   used_ = true;
   last_ = s;
-  return hipEventRecord(ev_, s);
+  return tracked_ ? hipEventRecord(ev_, s) : hipSuccess;
 }
 
 static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

@@ -147,6 +147,14 @@ bsm_status batch_run(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt, const 
 // host, so reuse never races with earlier work.
 class Scratch {
  public:
+  // tracked = true: every use is recorded with an event, so a use on another
+  // stream waits only for that event.  tracked = false (the single-pair
+  // entry points, called over and over on one stream): uses are not
+  // recorded; a use on another stream, growth and destruction wait for the
+  // whole device instead.  An event per call costs about 5 us of command
+  // processing on the stream, a device-wide wait only when the stream
+  // changes.
+  explicit Scratch(bool tracked = true) : tracked_(tracked) {}
   ~Scratch();
   // Returns a buffer of at least `bytes` usable on stream s (nullptr on
   // failure; *err holds the HIP error).
@@ -156,6 +164,8 @@ class Scratch {
   size_t capacity() const { return cap_; }
 
  private:
+  hipError_t wait_last_use();  // host waits until the last use has finished
+  bool tracked_;
   void *ptr_ = nullptr;
   size_t cap_ = 0;
   hipEvent_t ev_ = nullptr;
@@ -202,8 +212,8 @@ struct bsm_ctx {
   int2 *d_right_offs_m = nullptr;
   int left_pitch16_m = 0, left_pitch32_m = 0;
   std::mutex tune_mu;  // guards dt.tune between its setters and the serving thread
-  bsm::Scratch describe_scratch;  // packed colour plane of bsm_describe
-  bsm::Scratch match_scratch;     // planes + descriptors of bsm_match
+  bsm::Scratch describe_scratch{false};  // packed colour plane of bsm_describe
+  bsm::Scratch match_scratch{false};     // planes + descriptors of bsm_match
   bsm::SideLane side;             // other-view stream of bsm_match
   bool dead = false;
   std::string dead_reason;

@@ -71,10 +71,11 @@ def test_batch_persistent_equals_oracle(torch_cuda, bsm, orc, n, S, scale, want_
     ctx.close()
 
 
-def test_batch_without_mask(torch_cuda, bsm, orc):
-    _say("case: persistent batch, mask off (Eq. 4)")
+@pytest.mark.parametrize("want_cost", [True, False])
+def test_batch_without_mask(torch_cuda, bsm, orc, want_cost):
+    _say(f"case: persistent batch, mask off (Eq. 4), volume={want_cost}")
     ctx, pat = _ctx(bsm, orc, 256, 15, use_mask=False)
-    _check_batch_vs_oracle(torch_cuda, ctx, pat, orc, _scenes(5, 0.12), True, use_mask=False)
+    _check_batch_vs_oracle(torch_cuda, ctx, pat, orc, _scenes(5, 0.12), want_cost, use_mask=False)
     ctx.close()
 
 

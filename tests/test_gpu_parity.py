@@ -339,3 +339,27 @@ def test_device_calls_validate_arguments(torch_cuda, bsm, orc):
     assert lib.bsm_match(ctx.h, P(img), P(img), 8, 8, 24, 4, P(disp), None, None) == bsm.OK
     torch.cuda.synchronize()
     ctx.close()
+
+
+def test_match_alternating_streams(torch_cuda, bsm, orc):
+    # the single-pair scratch moves between streams: each call must see its
+    # own inputs and leave the previous call's results intact
+    torch = torch_cuda
+    _say("case: bsm_match alternating between two streams, pairs above 64 K pixels")
+    p = synth.CONFIG_PARAMS[0]
+    ctx, pat = _ctx(bsm, orc, p["n"], p["S"], seed=synth.PATTERN_SEED)
+    scenes = [synth.slanted_scene(40 + i, 320, 210, 30) for i in range(3)]
+    want = [orc.match(s.left, s.right, pat, 30)[0] for s in scenes]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for rep in range(2):
+        for i, s in enumerate(scenes):
+            st = streams[(i + rep) % 2]
+            with torch.cuda.stream(st):
+                L, R = _dev(torch, s.left), _dev(torch, s.right)
+                d, _ = ctx.match(L, R, 30, stream=st)
+                outs.append((i, d))
+    torch.cuda.synchronize()
+    for i, d in outs:
+        assert np.array_equal(d.cpu().numpy(), want[i]), i
+    ctx.close()
