@@ -165,10 +165,12 @@ bsm_status bsm_describe_packed(bsm_ctx *ctx, const uint32_t *packed, int32_t W,
                                void *hip_stream);
 
 /* Masked cost (Eq. 8, or Eq. 4 when maskL == NULL) fused with the
- * winner-take-all of Eq. 1.  The H x W x dmax volume is written only when
- * cost != NULL.  descL, maskL, descR: device uint64 [H][W][n/64];
- * disp: device int32 [H][W]; cost: device int16 [dmax][H][W] or NULL.
- * 1 <= dmax <= W. */
+ * winner-take-all of Eq. 1 (lowest d among equal costs).  The H x W x dmax
+ * volume is written only when cost != NULL; entries with u - d < 0 hold
+ * 32767.  descL, maskL, descR: device uint64 [H][W][n/64], 16-byte
+ * aligned; disp: device int32 [H][W]; cost: device int16 [dmax][H][W] or
+ * NULL.  1 <= dmax <= W.  The matrix-core and bitwise kernels (bsm_tuning
+ * cost_mfma) give identical results. */
 bsm_status bsm_cost_wta(bsm_ctx *ctx, const uint64_t *descL,
                         const uint64_t *maskL, const uint64_t *descR,
                         int32_t W, int32_t H, int32_t dmax, int32_t *disp,
@@ -243,7 +245,8 @@ bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs,
 /* Launch choices of a context.  They change speed only, never results. */
 typedef struct {
     int32_t desc_tile_w;      /* describe+mask tile width: 16 or 32 pixels   */
-    int32_t cost_dchunk;      /* disparities per cost LDS window: 32 or 64  */
+    int32_t cost_dchunk;      /* disparities per LDS window of the bitwise
+                                 cost kernel: 32 or 64                      */
     int32_t blocks_per_cu[4]; /* persistent batch launches, 0 = default:
                                  [0] colour, [1] the two describe stages
                                  (one launch), [3] cost: workgroups per CU
