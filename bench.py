@@ -136,6 +136,34 @@ def bench_batch(args):
         "scene_generation_s": round(gen_s, 2),
         "roofline": None,
     }
+    # The same 64 pairs at a quarter of the size (W 80-480, H 60-270, dmax
+    # 8-64): launch-bound pairs, where one persistent launch for all of them
+    # pays off.  Reported beside, not as the value.
+    small = [synth.batch_scene(s, scale=0.25) for s in specs]
+    s_items = [(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), sc.dmax)
+               for sc in small]
+    s_pairs, s_outs, s_keep = ctx._pairs(s_items, False)
+    s_arr = (_bsm.Pair * len(s_pairs))(*s_pairs)
+
+    def small_batch():
+        if lib.bsm_match_batch(ctx.h, s_arr, len(s_pairs), sp) != 0:
+            raise RuntimeError(_bsm.bsm_last_error())
+
+    def small_plain():
+        for p in s_pairs:
+            if lib.bsm_match(ctx.h, p.left, p.right, p.width, p.height, p.stride, p.dmax, p.disp,
+                             None, sp) != 0:
+                raise RuntimeError(_bsm.bsm_last_error())
+
+    ms_sb = timed(small_batch, steps, max(1, args.warmup))
+    s_disp = [o[0].clone() for o in s_outs]
+    ms_sp = timed(small_plain, steps, 1)
+    out["quarter_size_pairs"] = {
+        "ms_batch": ms_sb, "ms_plain": ms_sp, "batch_speedup_vs_plain": ms_sp / ms_sb,
+        "pairs_per_s_batch": len(small) / (ms_sb / 1e3),
+        "pairs_per_s_plain": len(small) / (ms_sp / 1e3),
+        "batch_equals_plain": all(torch.equal(a, o[0]) for a, o in zip(s_disp, s_outs)),
+    }
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -1567,7 +1567,10 @@ __global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restric
 }
 
 // The no-volume cost queues on the matrix cores: an item (a 128-pixel row
-// tile) goes to a workgroup of four waves, one 32-pixel tile each.
+// tile) gives each of the four waves one 32-pixel tile; a workgroup takes
+// kMfmaChunk consecutive items per queue pull, so that the pull (two
+// barriers and an atomic) stays small beside the work even at dmax = 32.
+constexpr int kMfmaChunk = 4;
 template <int NW, bool MASK>
 __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
     const BatchWork *__restrict__ bw) {
@@ -1582,19 +1585,22 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
     const int *start = bw->start + q * (n + 1);
     const int total = start[n];
     for (;;) {
-      const int cur = take(bw->counters + q, &slot);
-      if (cur >= total) break;
-      const int i = owner(start, n, cur);
-      const BatchPair &p = bw->pairs[bw->order[i]];
-      const int W = uniform(p.W);
-      const int tiles = (W + kCostTX - 1) / kCostTX;
-      const int local = cur - start[i];
-      const int v = x + kXcds * (local / tiles);
-      const int u0 = (local % tiles) * kCostTX + wave * kMfmaTX;
-      if (u0 < W)
-        cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
-                                 uniform(p.H), uniform(p.dmax), uniform(p.disp), nullptr,
-                                 nullptr, v, u0);
+      const int first = take(bw->counters + q, &slot) * kMfmaChunk;
+      if (first >= total) break;
+      int i = owner(start, n, first);
+      for (int cur = first; cur < first + kMfmaChunk && cur < total; ++cur) {
+        while (cur >= start[i + 1]) ++i;  // items of a chunk may cross pairs
+        const BatchPair &p = bw->pairs[bw->order[i]];
+        const int W = uniform(p.W);
+        const int tiles = (W + kCostTX - 1) / kCostTX;
+        const int local = cur - start[i];
+        const int v = x + kXcds * (local / tiles);
+        const int u0 = (local % tiles) * kCostTX + wave * kMfmaTX;
+        if (u0 < W)
+          cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
+                                   uniform(p.H), uniform(p.dmax), uniform(p.disp), nullptr,
+                                   nullptr, v, u0);
+      }
     }
   }
 }
