@@ -27,13 +27,15 @@ struct BatchState {
   // graph exists.  The tables (which grow with the batch) are only reached
   // through d_work.
   BatchWork *d_work = nullptr;
-  int *d_counters = nullptr;     // [kBatchQueues] queue heads
+  int *d_counters = nullptr;     // queue heads, kCounterStride ints apart
   char *d_tables = nullptr;      // pairs | order | start
   size_t d_tables_cap = 0;
   Tuning tune;                   // launch choices the graph was captured with
   char *h_stage = nullptr;       // pinned staging of BatchWork + tables
   size_t h_stage_cap = 0;
   hipEvent_t done = nullptr;     // last batch finished with the tables
+  hipEvent_t staged = nullptr;   // last batch's upload has read the staging buffer
+  hipStream_t last_stream = nullptr;  // stream of the last batch
   bool launched = false;
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
@@ -44,6 +46,7 @@ struct BatchState {
       if (launched) (void)hipEventSynchronize(done);
       (void)hipEventDestroy(done);
     }
+    if (staged) (void)hipEventDestroy(staged);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (capture) (void)hipStreamDestroy(capture);
@@ -77,8 +80,10 @@ bsm_status batch_state_create(bsm_ctx *ctx, BatchState **out) {
   hipError_t e;
   const size_t work_bytes = align_up(sizeof(BatchWork), 256);
   if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipMalloc(&b->d_work, work_bytes + kBatchQueues * sizeof(int))) != hipSuccess)
+      (e = hipMalloc(&b->d_work, work_bytes + kBatchQueues * kCounterStride * sizeof(int))) !=
+          hipSuccess)
     return device_fail(ctx, e, "batch state");
   b->d_counters = reinterpret_cast<int *>(reinterpret_cast<char *>(b->d_work) + work_bytes);
   *out = b.release();
@@ -164,13 +169,21 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
   const size_t table_bytes = align_up(off_start + kBatchQueues * n1 * sizeof(int), 256);
   const size_t stage_bytes = table_bytes + sizeof(BatchWork);
 
-  // The previous batch must be done with the staging buffer and the tables
-  // before either is rewritten.
-  if (b.launched && (e = hipEventSynchronize(b.done)) != hipSuccess)
-    return device_fail(ctx, e, "waiting for the previous batch");
-  // A graph captured with other launch choices does not match the tile
-  // numbering below: capture again.
-  if (b.exec && !same_tuning(b.tune, dt.tune)) b.drop_graph();
+  // The pinned staging buffer may be rewritten once the previous batch's
+  // upload has run, which is as soon as that batch starts.  The device
+  // tables and work list are rewritten by this batch's upload, queued on the
+  // same stream behind the previous batch's kernels, so only a change of
+  // stream, tables or staging that must grow, or a graph captured with other
+  // launch choices (it does not match the tile numbering below) make the
+  // host wait for the previous batch to finish.
+  const bool retune = b.exec && !same_tuning(b.tune, dt.tune);
+  if (b.launched) {
+    const bool drain = s != b.last_stream || retune || table_bytes > b.d_tables_cap ||
+                       stage_bytes > b.h_stage_cap;
+    if ((e = hipEventSynchronize(drain ? b.done : b.staged)) != hipSuccess)
+      return device_fail(ctx, e, "waiting for the previous batch");
+  }
+  if (retune) b.drop_graph();
   if (table_bytes > b.d_tables_cap) {
     if (b.d_tables) (void)hipFree(b.d_tables);
     b.d_tables = nullptr;
@@ -234,6 +247,7 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
       (e = hipMemcpyAsync(b.d_work, hw, sizeof(BatchWork), hipMemcpyHostToDevice, s)) !=
           hipSuccess)
     return device_fail(ctx, e, "uploading the batch work list");
+  if ((e = hipEventRecord(b.staged, s)) != hipSuccess) return device_fail(ctx, e, "batch event");
 
   const BatchLaunch bl{b.d_work, b.d_counters};
   if (!b.exec) {
@@ -259,6 +273,7 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
     return device_fail(ctx, e, "launching the batch graph");
   if ((e = hipEventRecord(b.done, s)) != hipSuccess) return device_fail(ctx, e, "batch event");
   b.launched = true;
+  b.last_stream = s;
   if ((e = b.scratch.release(s)) != hipSuccess) return device_fail(ctx, e, "batch scratch event");
   return BSM_OK;
 }

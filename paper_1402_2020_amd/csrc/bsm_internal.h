@@ -77,6 +77,9 @@ int choose_left_pitch(const int8_t *pattern, int n, int cols);
 constexpr int kQueueColor = 0, kQueueDescribeMask = 1, kQueueDescribe = 2, kQueueCost0 = 3;
 constexpr int kQueueCostVol0 = kQueueCost0 + 8;
 constexpr int kBatchQueues = kQueueCostVol0 + 8;
+// Queue heads sit 128 bytes apart, so that the atomics of different queues
+// do not contend for one cache line.
+constexpr int kCounterStride = 32;
 
 // One pair of a batch with its scratch planes.
 struct BatchPair {
@@ -94,7 +97,7 @@ struct BatchWork {
   const BatchPair *pairs;
   const int *order;
   const int *start;
-  int *counters;  // [kBatchQueues]
+  int *counters;  // head of queue q at counters[q * kCounterStride]
   int npairs;
 };
 

@@ -1437,17 +1437,57 @@ __device__ __forceinline__ int owner(const int *start, int npairs, int t) {
   return lo;
 }
 
-// Next item of a queue for the whole workgroup (broadcast through LDS; the
-// value is uniform, so everything derived from it stays in scalar registers).
-__device__ __forceinline__ int take(int *counter, int *slot) {
-  __syncthreads();  // everyone has read the previous value
-  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
-  __syncthreads();
-  return __builtin_amdgcn_readfirstlane(*slot);
+// Queue head read coherently across the XCDs.  Heads only grow during a
+// stage, so a head at or past a queue's length proves the queue drained and
+// spares the atomic that would only confirm it (every workgroup ends each
+// queue it visits with such a pull, on one counter).
+__device__ __forceinline__ int queue_head(int *counter) {
+  return __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A workgroup's pulls from one queue of `total` items (thread 0 pulls; the
+// value goes to every thread through LDS and is uniform, so everything
+// derived from it stays in scalar registers).  While at least a grid's
+// worth of items lies beyond the current one, the next item is claimed when
+// the current one starts, so the atomic's round trip overlaps the work;
+// near the end of the queue pulls wait for the current item, so that no
+// item waits behind a busy workgroup while others idle.
+struct WgQueue {
+  int *counter;
+  int total;
+  int *slot;
+  int claimed;  // thread 0: item claimed ahead, or -1
+  // First pull; `check` first reads the head (a queue likely drained).
+  __device__ __forceinline__ int first(bool check) {
+    int v = 0;
+    if (threadIdx.x == 0) {
+      const int h = check ? queue_head(counter) : 0;
+      v = h >= total ? h : atomicAdd(counter, 1);
+    }
+    return publish(v);
+  }
+  // Called when item `cur` starts.
+  __device__ __forceinline__ void begin(int cur) {
+    claimed = -1;
+    if (threadIdx.x == 0 && cur + static_cast<int>(gridDim.x) < total)
+      claimed = atomicAdd(counter, 1);
+  }
+  // Called when the current item is done: the next item.
+  __device__ __forceinline__ int next() {
+    int v = 0;
+    if (threadIdx.x == 0) v = claimed >= 0 ? claimed : atomicAdd(counter, 1);
+    return publish(v);
+  }
+  __device__ __forceinline__ int publish(int v) {
+    __syncthreads();  // everyone has read the previous value
+    if (threadIdx.x == 0) *slot = v;
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+  }
+};
+
 __global__ void k_batch_reset(int *counters) {
-  if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0;
+  if (threadIdx.x < kBatchQueues) counters[threadIdx.x * kCounterStride] = 0;
 }
 
 __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *__restrict__ bw,
@@ -1456,10 +1496,9 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
                                                                Mq mq, int use_mask) {
   __shared__ int slot;
   const int *start = bw->start + kQueueColor * (bw->npairs + 1);
-  const int total = start[bw->npairs];
-  for (;;) {
-    const int t = take(bw->counters + kQueueColor, &slot);
-    if (t >= total) break;
+  WgQueue qu{bw->counters + kQueueColor * kCounterStride, start[bw->npairs], &slot, -1};
+  for (int t = qu.first(false); t < qu.total; t = qu.next()) {
+    qu.begin(t);
     const int i = owner(start, bw->npairs, t);
     const BatchPair &p = bw->pairs[bw->order[i]];
     const int tx = (p.W + kColorTX - 1) / kColorTX;
@@ -1488,10 +1527,10 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
   for (int phase = 0; phase < 2; ++phase) {
     if ((phase == 0) == right_first) {
       const int *start = bw->start + kQueueDescribe * (n + 1);
-      const int total = start[n];
-      for (;;) {
-        const int t = take(bw->counters + kQueueDescribe, &slot);
-        if (t >= total) break;
+      WgQueue qu{bw->counters + kQueueDescribe * kCounterStride, start[n], &slot, -1};
+      if (qu.total == 0) continue;
+      for (int t = qu.first(phase == 1); t < qu.total; t = qu.next()) {
+        qu.begin(t);
         const int i = owner(start, n, t);
         const BatchPair &p = bw->pairs[bw->order[i]];
         const int W = uniform(p.W), H = uniform(p.H);
@@ -1505,10 +1544,10 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
       }
     } else {
       const int *start = bw->start + kQueueDescribeMask * (n + 1);
-      const int total = start[n];
-      for (;;) {
-        const int t = take(bw->counters + kQueueDescribeMask, &slot);
-        if (t >= total) break;
+      WgQueue qu{bw->counters + kQueueDescribeMask * kCounterStride, start[n], &slot, -1};
+      if (qu.total == 0) continue;
+      for (int t = qu.first(phase == 1); t < qu.total; t = qu.next()) {
+        qu.begin(t);
         const int i = owner(start, n, t);
         const BatchPair &p = bw->pairs[bw->order[i]];
         const int W = uniform(p.W), H = uniform(p.H);
@@ -1522,12 +1561,24 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
   }
 }
 
-// Next item of a queue for a one-wave workgroup: lane 0 adds, every lane
-// reads the result.
-__device__ __forceinline__ int wave_take(int *counter) {
+// Pulls of one wave on its own (no barrier): lane 0 adds.  claim() starts a
+// pull and returns lane 0's pending value; value() makes it the wave's,
+// waiting for the atomic only then, so a pull started before an item's work
+// overlaps it.
+__device__ __forceinline__ int wave_claim(int *counter) {
   int t = 0;
-  if (threadIdx.x == 0) t = atomicAdd(counter, 1);
-  return __builtin_amdgcn_readfirstlane(t);
+  if ((threadIdx.x & 63) == 0) t = atomicAdd(counter, 1);
+  return t;
+}
+__device__ __forceinline__ int wave_value(int claimed) {
+  return __builtin_amdgcn_readfirstlane(claimed);
+}
+// A queue a wave visits after its own: drained when its head has reached
+// its length.
+__device__ __forceinline__ bool wave_drained(int *counter, int total) {
+  int h = 0;
+  if ((threadIdx.x & 63) == 0) h = queue_head(counter);
+  return __builtin_amdgcn_readfirstlane(h) >= total;
 }
 
 // Cost tiles.  Queue x (one per XCD) holds the tiles of the rows v = x mod 8
@@ -1546,11 +1597,12 @@ __global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restric
     const int q = (VOL ? kQueueCostVol0 : kQueueCost0) + x;
     const int *start = bw->start + q * (n + 1);
     const int total = start[n];
-    int *counter = bw->counters + q;
-    int cur = wave_take(counter);
+    int *counter = bw->counters + q * kCounterStride;
+    if (total == 0 || (qi > 0 && wave_drained(counter, total))) continue;
+    int cur = wave_value(wave_claim(counter));
     int i = 0, i_end = -1;  // pair of the last item and the end of its range
     while (cur < total) {
-      const int next = wave_take(counter);
+      const int next = wave_claim(counter);
       if (cur >= i_end || cur < start[i]) {
         i = owner(start, n, cur);
         i_end = start[i + 1];
@@ -1561,22 +1613,20 @@ __global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restric
       cost_tile<NW, DC, MASK, VOL>(win, p.descL, p.maskL, p.descR, p.W, p.H, p.dmax, p.disp,
                                    p.cost, x + kXcds * (local / tiles),
                                    (local % tiles) * kCostTX);
-      cur = next;
+      cur = wave_value(next);
     }
   }
 }
 
-// The no-volume cost queues on the matrix cores: an item (a 128-pixel row
-// tile) gives each of the four waves one 32-pixel tile; a workgroup takes
-// kMfmaChunk consecutive items per queue pull, so that the pull (two
-// barriers and an atomic) stays small beside the work even at dmax = 32.
-constexpr int kMfmaChunk = 4;
+// The no-volume cost queues on the matrix cores.  An item is a 128-pixel
+// row tile, and each wave pulls items on its own and runs their four 32-pixel
+// tiles: the waves of a workgroup share nothing, so they never wait for one
+// another at a barrier (at two waves per SIMD an idle wave costs half the
+// SIMD).  The next item is claimed before the current one runs.
 template <int NW, bool MASK>
 __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
     const BatchWork *__restrict__ bw) {
-  static_assert(kCostTX == kMfmaWaves * kMfmaTX, "an item is one tile per wave");
-  __shared__ int slot;
-  const int wave = threadIdx.x >> 6;
+  static_assert(kCostTX == kMfmaWaves * kMfmaTX, "an item is four matrix-core tiles");
   const int home = blockIdx.x % kXcds;
   const int n = bw->npairs;
   for (int qi = 0; qi < kXcds; ++qi) {
@@ -1584,23 +1634,30 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
     const int q = kQueueCost0 + x;
     const int *start = bw->start + q * (n + 1);
     const int total = start[n];
-    for (;;) {
-      const int first = take(bw->counters + q, &slot) * kMfmaChunk;
-      if (first >= total) break;
-      int i = owner(start, n, first);
-      for (int cur = first; cur < first + kMfmaChunk && cur < total; ++cur) {
-        while (cur >= start[i + 1]) ++i;  // items of a chunk may cross pairs
-        const BatchPair &p = bw->pairs[bw->order[i]];
-        const int W = uniform(p.W);
-        const int tiles = (W + kCostTX - 1) / kCostTX;
-        const int local = cur - start[i];
-        const int v = x + kXcds * (local / tiles);
-        const int u0 = (local % tiles) * kCostTX + wave * kMfmaTX;
+    int *counter = bw->counters + q * kCounterStride;
+    if (total == 0 || (qi > 0 && wave_drained(counter, total))) continue;
+    int cur = wave_value(wave_claim(counter));
+    int i = 0, i_end = -1;  // pair of the last item and the end of its range
+    while (cur < total) {
+      const int next = wave_claim(counter);
+      if (cur >= i_end || cur < start[i]) {
+        i = owner(start, n, cur);
+        i_end = start[i + 1];
+      }
+      const BatchPair &p = bw->pairs[bw->order[i]];
+      const int W = uniform(p.W);
+      const int tiles = (W + kCostTX - 1) / kCostTX;
+      const int local = cur - start[i];
+      const int v = x + kXcds * (local / tiles);
+      const int u_item = (local % tiles) * kCostTX;
+      for (int k = 0; k < kMfmaWaves; ++k) {
+        const int u0 = u_item + k * kMfmaTX;
         if (u0 < W)
           cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
                                    uniform(p.H), uniform(p.dmax), uniform(p.disp), nullptr,
                                    nullptr, v, u0);
       }
+      cur = wave_value(next);
     }
   }
 }

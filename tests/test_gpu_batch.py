@@ -132,6 +132,30 @@ def test_batch_graph_replays_as_the_pair_count_grows_and_shrinks(torch_cuda, bsm
     ctx.close()
 
 
+def test_batches_queued_back_to_back(torch_cuda, bsm, orc):
+    # Batches queued with no wait in between: each one rewrites the pinned
+    # staging buffer and the device tables while the previous batch may
+    # still run (the tables grow once, and one batch goes to another
+    # stream, which makes the next one wait for it).
+    torch = torch_cuda
+    _say("case: five batches queued back to back, 2/3/2/6/2 pairs, one on a second stream")
+    ctx, pat = _ctx(bsm, orc, 256, 15)
+    groups = [_scenes(2, 0.1, first=30), _scenes(3, 0.12, first=32), _scenes(2, 0.08, first=35),
+              _scenes(6, 0.1, first=37), _scenes(2, 0.1, first=43)]
+    want = [[orc.match(s.left, s.right, pat, s.dmax)[0] for s in g] for g in groups]
+    items = [[(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in g] for g in groups]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for k, group in enumerate(items):
+        outs.append(ctx.match_batch(group, stream=side if k == 2 else None))
+    torch.cuda.synchronize()
+    for k, (group_out, group_want) in enumerate(zip(outs, want)):
+        for j, ((disp, _), wd) in enumerate(zip(group_out, group_want)):
+            assert np.array_equal(disp.cpu().numpy(), wd), (k, j)
+    ctx.close()
+
+
 def test_batch_equals_single_pair_path_full_size(torch_cuda, bsm, orc):
     torch = torch_cuda
     _say("case: batch of 6 full-size uneven pairs == single-pair path")
