@@ -258,6 +258,9 @@ typedef struct {
                                  n <= 1024 and 16 < dmax (<= 256 with a
                                  volume; single pairs, and batch pairs
                                  without one); 0: the bitwise VALU kernel */
+    int32_t batch_tile_h;     /* describe+mask tile height of the persistent
+                                 batch: 8 or 16 rows (default 16; single
+                                 pairs choose their own)                    */
 } bsm_tuning;
 
 bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out);

@@ -58,11 +58,13 @@ class ServeCounters(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("desc_tile_w", C.c_int32), ("cost_dchunk", C.c_int32),
-                ("blocks_per_cu", C.c_int32 * 4), ("cost_mfma", C.c_int32)]
+                ("blocks_per_cu", C.c_int32 * 4), ("cost_mfma", C.c_int32),
+                ("batch_tile_h", C.c_int32)]
 
     def as_dict(self):
         return {"desc_tile_w": self.desc_tile_w, "cost_dchunk": self.cost_dchunk,
-                "blocks_per_cu": list(self.blocks_per_cu), "cost_mfma": self.cost_mfma}
+                "blocks_per_cu": list(self.blocks_per_cu), "cost_mfma": self.cost_mfma,
+                "batch_tile_h": self.batch_tile_h}
 
     @classmethod
     def from_dict(cls, d):
@@ -72,6 +74,7 @@ class Tuning(C.Structure):
         for i, v in enumerate(d.get("blocks_per_cu", [0, 0, 0, 0])):
             t.blocks_per_cu[i] = int(v)
         t.cost_mfma = int(d.get("cost_mfma", 1))
+        t.batch_tile_h = int(d.get("batch_tile_h", 16))
         return t
 
 

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <vector>
 
 #include "bsm_internal.h"
 
@@ -130,7 +131,7 @@ bsm_status batch_sequential(bsm_ctx *ctx, BatchState &b, const bsm_pair *pairs, 
 
 bool same_tuning(const Tuning &a, const Tuning &b) {
   if (a.desc_tile_w != b.desc_tile_w || a.cost_dchunk != b.cost_dchunk ||
-      a.cost_mfma != b.cost_mfma)
+      a.cost_mfma != b.cost_mfma || a.batch_tile_h != b.batch_tile_h)
     return false;
   for (int i = 0; i < 4; ++i)
     if (a.blocks_per_cu[i] != b.blocks_per_cu[i]) return false;
@@ -233,6 +234,7 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
     horder[i] = order[i];
     int counts[kBatchQueues];
     batch_tile_counts(p.width, p.height, use_mask, p.cost != nullptr, dt.tune.desc_tile_w,
+                      dt.tune.batch_tile_h,
                       counts);
     for (int q = 0; q < kBatchQueues; ++q) hstart[q * n1 + i + 1] = hstart[q * n1 + i] + counts[q];
   }
@@ -353,36 +355,47 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
   }
   Tuning best_t = ctx->dt.tune;
   double best_time = -1;
-  // Candidates: describe tile width x cost window (pairs with a volume) x
-  // cost persistent occupancy x share of the describe workgroups that
-  // start on the descriptor-only tiles.  Each runs on a copy of the tables;
-  // the batch state recaptures its graph whenever the launch choices change.
+  // Candidates: describe tile width x height x cost window (only when a
+  // pair has a volume: it is the bitwise kernel's) x cost persistent
+  // occupancy x share of the describe workgroups that start on the
+  // descriptor-only tiles.  Each runs on a copy of the tables; the batch
+  // state recaptures its graph whenever the launch choices change.
+  bool any_volume = false;
+  for (int i = 0; i < npairs; ++i) any_volume = any_volume || pairs[i].cost != nullptr;
+  std::vector<Tuning> candidates;
   for (int tw : {16, 32})
-    for (int dc : {32, 64})
-      for (int cost_bpc : {0, 2})
-        for (int right_every : {4, 8}) {
-          DeviceTables dt = ctx->dt;
-          dt.tune = Tuning();
-          dt.tune.desc_tile_w = tw;
-          dt.tune.cost_dchunk = dc;
-          dt.tune.blocks_per_cu[2] = right_every;
-          dt.tune.blocks_per_cu[3] = cost_bpc;
-          // one untimed run (captures the graph), then the timed runs
-          if ((st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s)) != BSM_OK) break;
-          if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
-          for (int r = 0; r < reps && st == BSM_OK; ++r)
-            st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s);
-          if (st != BSM_OK) break;
-          if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
-            break;
-          float ms = 0;
-          if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
-          const double per = ms / reps;
-          if (best_time < 0 || per < best_time) {
-            best_time = per;
-            best_t = dt.tune;
+    for (int th : {8, 16})
+      for (int dc : {32, 64})
+        for (int cost_bpc : {0, 2})
+          for (int right_every : {4, 8}) {
+            if (dc == 32 && !any_volume) continue;
+            Tuning t;
+            t.desc_tile_w = tw;
+            t.batch_tile_h = th;
+            t.cost_dchunk = dc;
+            t.blocks_per_cu[2] = right_every;
+            t.blocks_per_cu[3] = cost_bpc;
+            candidates.push_back(t);
           }
-        }
+  for (const Tuning &cand : candidates) {
+    DeviceTables dt = ctx->dt;
+    dt.tune = cand;
+    // one untimed run (captures the graph), then the timed runs
+    if ((st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s)) != BSM_OK) break;
+    if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+    for (int r = 0; r < reps && st == BSM_OK; ++r)
+      st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s);
+    if (st != BSM_OK) break;
+    if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
+      break;
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+    const double per = ms / reps;
+    if (best_time < 0 || per < best_time) {
+      best_time = per;
+      best_t = cand;
+    }
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (st == BSM_OK && e != hipSuccess) st = device_fail(ctx, e, "autotune timing");
@@ -396,6 +409,7 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
     best->cost_dchunk = best_t.cost_dchunk;
     for (int i = 0; i < 4; ++i) best->blocks_per_cu[i] = best_t.blocks_per_cu[i];
     best->cost_mfma = best_t.cost_mfma;
+    best->batch_tile_h = best_t.batch_tile_h;
   }
   if (best_ms) *best_ms = best_time;
   return BSM_OK;

@@ -614,6 +614,7 @@ bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out) {
   out->cost_dchunk = t.cost_dchunk;
   for (int i = 0; i < 4; ++i) out->blocks_per_cu[i] = t.blocks_per_cu[i];
   out->cost_mfma = t.cost_mfma;
+  out->batch_tile_h = t.batch_tile_h;
   return BSM_OK;
 }
 
@@ -630,11 +631,14 @@ bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *in) {
     if (in->blocks_per_cu[i] < 0 || in->blocks_per_cu[i] > 64)
       return fail(BSM_EINVAL, "blocks_per_cu[%d] out of [0, 64]", i);
   if (in->cost_mfma != 0 && in->cost_mfma != 1) return fail(BSM_EINVAL, "cost_mfma must be 0 or 1");
+  if (in->batch_tile_h != 8 && in->batch_tile_h != 16)
+    return fail(BSM_EINVAL, "batch_tile_h must be 8 or 16");
   Tuning t;
   t.desc_tile_w = in->desc_tile_w;
   t.cost_dchunk = in->cost_dchunk;
   for (int i = 0; i < 4; ++i) t.blocks_per_cu[i] = in->blocks_per_cu[i];
   t.cost_mfma = in->cost_mfma;
+  t.batch_tile_h = in->batch_tile_h;
   {
     // batch states compare this with the choices their graphs hold
     std::lock_guard<std::mutex> lk(ctx->tune_mu);

@@ -47,6 +47,7 @@ struct Tuning {
   int cost_dchunk = 64;                // disparities per cost LDS window: 32 or 64
   int blocks_per_cu[4] = {0, 0, 0, 0};  // persistent batch grids (0: all that fit)
   int cost_mfma = 1;                    // no-volume cost + WTA on the matrix cores
+  int batch_tile_h = 16;                // describe+mask tile height of the batch: 8 or 16
 };
 
 // Device-side view of the constant data of a context.
@@ -133,7 +134,7 @@ hipError_t launch_batch(const BatchLaunch &bl, const DeviceTables &t, int use_ma
 bool batch_supported(int nw);
 // Tiles per stage of one pair, as the batch kernels number them.
 void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
-                       int counts[kBatchQueues]);
+                       int desc_tile_h, int counts[kBatchQueues]);
 
 // ---- batch (bsm_batch.cpp) --------------------------------------------------
 struct BatchState;

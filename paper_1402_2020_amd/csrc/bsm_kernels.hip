@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL
 // Tile height (rows) of the describe+mask tiles: eight rows when the image
 // has tiles enough to fill the GPU several times over (fewer halo rows per
 // output row), four rows otherwise (twice the tiles, shorter tails).  The
-// persistent batch kernel always takes eight.
+// persistent batch kernel takes the height its tuning names (8 or 16 rows).
 constexpr int kDescTH = 8, kDescTHSmall = 4, kDescThreads = 256;
 constexpr long long kDescTallMinTiles = 4096;  // four rounds of the GPU at four blocks per CU
 constexpr int kGallopStep = 8;  // first step of the threshold search
@@ -341,8 +341,13 @@ struct DescribeConsts {
   int nw, radius, pitch, k;
 };
 
-template <int NW, int TW, int TH>
-__device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
+// Rows of the tile go to the waves either fixed (TH / 4 consecutive rows
+// each) or, with PULL_ROWS, one at a time from the LDS counter *row_next as
+// the waves become free: a wave whose pixels needed fewer search probes then
+// takes another row instead of waiting at the next barrier of a persistent
+// kernel for the others.
+template <int NW, int TW, int TH, bool PULL_ROWS>
+__device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next,
                                                    const uint32_t *__restrict__ packed, int W,
                                                    int H, const DescribeConsts &c,
                                                    uint64_t *__restrict__ desc,
@@ -393,14 +398,25 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile,
     }
   }
   const int k_eff = c.k + (64 * NW - n);
+  if (PULL_ROWS && threadIdx.x == 0) *row_next = 0;
   __syncthreads();
 
   const char *lds = reinterpret_cast<const char *>(tile);
   constexpr int kRowsPerWave = TH / (kDescThreads / 64);
   constexpr int kGroup = 4;  // pixels whose LDS addresses share one base
   int guess = 64;            // threshold search start: the previous pixel's T
-  for (int r = 0; r < kRowsPerWave; ++r) {
-    const int ty = wave * kRowsPerWave + r, v = v0 + ty;
+  for (int r = 0;; ++r) {
+    int ty;
+    if constexpr (PULL_ROWS) {
+      int pulled = 0;
+      if (lane == 0) pulled = atomicAdd(row_next, 1);
+      ty = __builtin_amdgcn_readfirstlane(pulled);
+      if (ty >= TH) break;  // uniform
+    } else {
+      if (r == kRowsPerWave) break;
+      ty = wave * kRowsPerWave + r;
+    }
+    const int v = v0 + ty;
     if (v >= H) break;  // uniform
     for (int g = 0; g < TW; g += kGroup) {
       if (u0 + g >= W) break;  // uniform
@@ -428,8 +444,8 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
-  describe_mask_tile<NW, TW, TH>(tile, packed, W, H, c, desc, mask, blockIdx.x * TW,
-                                 blockIdx.y * TH);
+  describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, desc, mask,
+                                        blockIdx.x * TW, blockIdx.y * TH);
 }
 
 // ===========================================================================
@@ -1516,12 +1532,12 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
 // describe+mask queue, and each turns to the other queue when its own is
 // empty: the LDS-bound descriptor-only tiles and the issue-bound
 // describe+mask tiles share the CUs instead of following each other.
-template <int NW, int TW>
+template <int NW, int TW, int TH>
 __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
     const BatchWork *__restrict__ bw, DescribeConsts cm, RightConsts cr, int right_every) {
   static_assert(kDescThreads == kRightThreads, "one workgroup shape for both stages");
   extern __shared__ uint32_t dlds[];
-  __shared__ int slot;
+  __shared__ int slot, row_next;
   const int n = bw->npairs;
   const bool right_first = blockIdx.x % right_every == 0;
   for (int phase = 0; phase < 2; ++phase) {
@@ -1553,9 +1569,9 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
         const int W = uniform(p.W), H = uniform(p.H);
         const int tx = (W + TW - 1) / TW;
         const int local = t - start[i];
-        describe_mask_tile<NW, TW, kDescTH>(dlds, uniform(p.packedL), W, H, cm,
-                                            uniform(p.descL), uniform(p.maskL),
-                                            (local % tx) * TW, (local / tx) * kDescTH);
+        describe_mask_tile<NW, TW, TH, true>(dlds, &row_next, uniform(p.packedL), W, H, cm,
+                                             uniform(p.descL), uniform(p.maskL),
+                                             (local % tx) * TW, (local / tx) * TH);
       }
     }
   }
@@ -1784,7 +1800,7 @@ int persistent_grid(K kernel, int threads, size_t lds, int per_cu) {
   return std::max(kXcds, (cus * k + kXcds - 1) / kXcds * kXcds);
 }
 
-template <int NW, int TW, int DC>
+template <int NW, int TW, int TH, int DC>
 hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
                           hipStream_t s) {
   const Tuning &tu = t.tune;
@@ -1796,17 +1812,17 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
   {
     // both describe stages (the describe+mask queue is empty without a mask)
     static const hipError_t attr =
-        allow_big_lds(reinterpret_cast<const void *>(k_batch_describe<NW, TW>));
+        allow_big_lds(reinterpret_cast<const void *>(k_batch_describe<NW, TW, TH>));
     if (attr != hipSuccess) return attr;
     DescribeConsts cm = describe_consts(t);
     cm.pitch = t.left_pitch_for(TW);
-    const size_t lds = std::max(mask_lds_bytes(t, TW), right_lds_bytes(kRightPx, t.radius,
-                                                                        t.right_pitch));
-    const int g1 = persistent_grid(k_batch_describe<NW, TW>, kDescThreads, lds,
+    const size_t lds = std::max(mask_lds_bytes(t, TW, TH),
+                                right_lds_bytes(kRightPx, t.radius, t.right_pitch));
+    const int g1 = persistent_grid(k_batch_describe<NW, TW, TH>, kDescThreads, lds,
                                    tu.blocks_per_cu[1]);
     const int right_every = tu.blocks_per_cu[2] > 0 ? tu.blocks_per_cu[2] : kDescRightEvery;
-    hipLaunchKernelGGL((k_batch_describe<NW, TW>), dim3(g1), dim3(kDescThreads), lds, s, bw, cm,
-                       right_consts(t), use_mask ? right_every : 1);
+    hipLaunchKernelGGL((k_batch_describe<NW, TW, TH>), dim3(g1), dim3(kDescThreads), lds, s, bw,
+                       cm, right_consts(t), use_mask ? right_every : 1);
   }
   {
     // pairs without a volume, then pairs with one (each kernel's queues are
@@ -1838,11 +1854,18 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
   return hipGetLastError();
 }
 
+template <int NW, int TW, int TH>
+hipError_t launch_batch_th(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
+                           hipStream_t s) {
+  return t.tune.cost_dchunk == 32 ? launch_batch_t<NW, TW, TH, 32>(bl, t, use_mask, s)
+                                  : launch_batch_t<NW, TW, TH, 64>(bl, t, use_mask, s);
+}
+
 template <int NW, int TW>
 hipError_t launch_batch_tw(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
                            hipStream_t s) {
-  return t.tune.cost_dchunk == 32 ? launch_batch_t<NW, TW, 32>(bl, t, use_mask, s)
-                                  : launch_batch_t<NW, TW, 64>(bl, t, use_mask, s);
+  return t.tune.batch_tile_h == 8 ? launch_batch_th<NW, TW, 8>(bl, t, use_mask, s)
+                                  : launch_batch_th<NW, TW, 16>(bl, t, use_mask, s);
 }
 
 template <int NW>
@@ -1862,11 +1885,12 @@ int describe_right_cols(int radius) {
 }
 
 void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
-                       int counts[kBatchQueues]) {
+                       int desc_tile_h, int counts[kBatchQueues]) {
   counts[kQueueColor] =
       2 * ((W + kColorTX - 1) / kColorTX) * ((H + kBatchColorTY - 1) / kBatchColorTY);
   counts[kQueueDescribeMask] =
-      use_mask ? ((W + desc_tile_w - 1) / desc_tile_w) * ((H + kDescTH - 1) / kDescTH) : 0;
+      use_mask ? ((W + desc_tile_w - 1) / desc_tile_w) * ((H + desc_tile_h - 1) / desc_tile_h)
+               : 0;
   counts[kQueueDescribe] =
       (use_mask ? 1 : 2) * ((W + kRightTW - 1) / kRightTW) * ((H + kRightTH - 1) / kRightTH);
   const int tiles = (W + kCostTX - 1) / kCostTX;

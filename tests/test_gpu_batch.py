@@ -176,7 +176,8 @@ def test_batch_equals_single_pair_path_full_size(torch_cuda, bsm, orc):
     ctx.close()
 
 
-TUNINGS = [dict(desc_tile_w=tw, cost_dchunk=dc, blocks_per_cu=[0, bm, 0, bc], cost_mfma=mf)
+TUNINGS = [dict(desc_tile_w=tw, cost_dchunk=dc, blocks_per_cu=[0, bm, 0, bc], cost_mfma=mf,
+                batch_tile_h=8 if dc == 32 else 16)
            for tw in (16, 32) for dc in (32, 64) for bm, bc in ((0, 0), (2, 1)) for mf in (1, 0)
            if mf == 1 or (bm, bc) == (0, 0)]
 _TUNING_SCENE = {}
@@ -190,8 +191,9 @@ def _tuning_scene(orc, pat):
     return _TUNING_SCENE[key]
 
 
-@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"tw{t['desc_tile_w']}-dc{t['cost_dchunk']}-"
-                         f"b{t['blocks_per_cu'][1]}{t['blocks_per_cu'][3]}-mfma{t['cost_mfma']}")
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"tw{t['desc_tile_w']}-th{t['batch_tile_h']}-"
+                         f"dc{t['cost_dchunk']}-b{t['blocks_per_cu'][1]}{t['blocks_per_cu'][3]}-"
+                         f"mfma{t['cost_mfma']}")
 def test_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
     # single pair with and without a volume, and a persistent two-pair batch
     # with and without volumes, under each launch choice
@@ -222,7 +224,8 @@ def test_set_tuning_validates(torch_cuda, bsm, orc):
     ctx, _ = _ctx(bsm, orc, 256, 15)
     for bad in (dict(desc_tile_w=8, cost_dchunk=64), dict(desc_tile_w=16, cost_dchunk=48),
                 dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 65]),
-                dict(desc_tile_w=16, cost_dchunk=64, cost_mfma=2)):
+                dict(desc_tile_w=16, cost_dchunk=64, cost_mfma=2),
+                dict(desc_tile_w=16, cost_dchunk=64, batch_tile_h=12)):
         assert bsm.bsm_set_tuning(ctx.h, bsm.Tuning.from_dict(bad)) == bsm.EINVAL
     ctx.close()
 
