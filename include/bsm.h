@@ -236,9 +236,11 @@ bsm_status bsm_vote_refine(bsm_ctx *ctx, const uint8_t *left, int32_t W,
  * graph that every later batch replays, whatever its shapes.  All pointers
  * in `pairs` are device pointers; `pairs` itself is host memory.  Results
  * equal npairs calls of bsm_match.  The persistent path needs n in
- * {64, 128, 256, 512, 1024} and at least two pairs; otherwise the pairs run
- * one after another with the per-pair kernels.  Uses context scratch (the
- * sum of the pairs' bsm_footprint without volumes). */
+ * {64, 128, 256, 512, 1024} and at least five pairs; otherwise the pairs
+ * run one after another with the per-pair kernels (on up to four pairs they
+ * are faster than the persistent launch, whose fixed cost is about 0.1 ms).
+ * Uses context scratch (the sum of the pairs' bsm_footprint without
+ * volumes). */
 bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs,
                            int32_t npairs, void *hip_stream);
 

@@ -90,8 +90,8 @@ def test_batch_graph_reused_across_shapes_and_replays(torch_cuda, bsm, orc):
     torch = torch_cuda
     _say("case: batch graph replays with different shapes and eager work between")
     ctx, pat = _ctx(bsm, orc, 256, 15)
-    first = _scenes(4, 0.1)
-    second = _scenes(6, 0.13, first=10)
+    first = _scenes(5, 0.1)
+    second = _scenes(7, 0.13, first=10)
     want = {}
     for s in first + second:
         want[id(s)] = orc.match(s.left, s.right, pat, s.dmax)[0]
@@ -113,13 +113,13 @@ def test_batch_graph_replays_as_the_pair_count_grows_and_shrinks(torch_cuda, bsm
     # the current batch only: the tables are reallocated when a batch needs
     # more pairs than any before it, and their layout moves with the count.
     torch = torch_cuda
-    _say("case: batch graph replays with 1, 9, 3, 12 pairs, tuning changed between")
+    _say("case: batch graph replays with 5, 9, 6, 12 pairs (and 2 pair by pair), tuning changed")
     ctx, pat = _ctx(bsm, orc, 256, 15)
     scenes = _scenes(12, 0.08, first=20)
     want = [orc.match(s.left, s.right, pat, s.dmax)[0] for s in scenes]
     tunings = [None, dict(desc_tile_w=32, cost_dchunk=32, blocks_per_cu=[0, 2, 0, 1]), None,
-               dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 0])]
-    for count, tune in zip((1, 9, 3, 12), tunings):
+               dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 0]), None]
+    for count, tune in zip((5, 9, 6, 12, 2), tunings):
         if tune is not None:
             ctx.set_tuning(tune)
         group = list(range(count))
@@ -138,10 +138,10 @@ def test_batches_queued_back_to_back(torch_cuda, bsm, orc):
     # still run (the tables grow once, and one batch goes to another
     # stream, which makes the next one wait for it).
     torch = torch_cuda
-    _say("case: five batches queued back to back, 2/3/2/6/2 pairs, one on a second stream")
+    _say("case: five batches queued back to back, 5/6/5/9/5 pairs, one on a second stream")
     ctx, pat = _ctx(bsm, orc, 256, 15)
-    groups = [_scenes(2, 0.1, first=30), _scenes(3, 0.12, first=32), _scenes(2, 0.08, first=35),
-              _scenes(6, 0.1, first=37), _scenes(2, 0.1, first=43)]
+    groups = [_scenes(5, 0.1, first=30), _scenes(6, 0.12, first=35), _scenes(5, 0.08, first=41),
+              _scenes(9, 0.1, first=46), _scenes(5, 0.1, first=55)]
     want = [[orc.match(s.left, s.right, pat, s.dmax)[0] for s in g] for g in groups]
     items = [[(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in g] for g in groups]
     side = torch.cuda.Stream()
@@ -195,8 +195,8 @@ def _tuning_scene(orc, pat):
                          f"dc{t['cost_dchunk']}-b{t['blocks_per_cu'][1]}{t['blocks_per_cu'][3]}-"
                          f"mfma{t['cost_mfma']}")
 def test_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
-    # single pair with and without a volume, and a persistent two-pair batch
-    # with and without volumes, under each launch choice
+    # single pair with and without a volume, and a persistent five-pair
+    # batch with and without volumes, under each launch choice
     torch = torch_cuda
     _say(f"case: tuning {tuning}")
     ctx, pat = _ctx(bsm, orc, 1024, 31, seed=11)
@@ -206,8 +206,8 @@ def test_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
     L, R = _dev(torch, sc.left), _dev(torch, sc.right)
     disp, cost = ctx.match(L, R, sc.dmax, want_cost=True)
     disp_nv, _ = ctx.match(L, R, sc.dmax, want_cost=False)
-    outs = ctx.match_batch([(L, R, sc.dmax)] * 2, want_cost=False)
-    outs_v = ctx.match_batch([(L, R, sc.dmax)] * 2, want_cost=True)
+    outs = ctx.match_batch([(L, R, sc.dmax)] * 5, want_cost=False)
+    outs_v = ctx.match_batch([(L, R, sc.dmax)] * 5, want_cost=True)
     torch.cuda.synchronize()
     assert np.array_equal(disp.cpu().numpy(), wd)
     assert np.array_equal(cost.cpu().numpy(), wc)
@@ -234,7 +234,7 @@ def test_autotune_picks_a_candidate_and_keeps_results(torch_cuda, bsm, orc):
     torch = torch_cuda
     _say("case: autotune on a small uneven batch")
     ctx, pat = _ctx(bsm, orc, 256, 15)
-    scenes = _scenes(4, 0.15)
+    scenes = _scenes(5, 0.15)
     items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
     best, ms = ctx.autotune(items, reps=2)
     assert best in TUNINGS or best["desc_tile_w"] in (16, 32)

@@ -78,8 +78,10 @@ def test_serve_mix_equals_oracle(torch_cuda, bsm, orc):
 def test_serve_groups_of_growing_size_on_one_slot(torch_cuda, bsm, orc):
     # One pair first (each slot's first batch is small), then bursts that
     # form larger groups on the same slots, with the tuning changed between.
-    _say("case: serving bursts of 1, 12, 5 pairs, tuning changed between")
+    _say("case: serving bursts of 1, 12, 5 pairs in groups of up to 8, tuning changed between")
     ctx, pat = _ctx(bsm, orc, 256, 15)
+    # groups of five or more pairs run as persistent batches
+    ctx.serve_config(8 << 30, 1024, 8)
     scenes = _scenes(12, 0.1, first=30)
     want = [orc.match(s.left, s.right, pat, s.dmax)[0] for s in scenes]
     for burst, tune in ((1, None), (12, dict(desc_tile_w=32, cost_dchunk=32,
