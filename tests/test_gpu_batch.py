@@ -79,6 +79,37 @@ def test_batch_without_mask(torch_cuda, bsm, orc, want_cost):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,S,want_cost", [(256, 15, True), (1024, 31, False)])
+def test_batch_degenerate_pairs(torch_cuda, bsm, orc, n, S, want_cost):
+    # Pairs at the edges of the method in one persistent batch: a single
+    # pixel, rows shorter than a tile, dmax = W, fewer rows than XCD queues
+    # (empty cost queues), a ragged tall pair.
+    torch = torch_cuda
+    sizes = [(1, 1, 1), (3, 2, 3), (64, 1, 64), (33, 17, 33), (130, 5, 100), (7, 41, 2)]
+    _say(f"case: persistent batch of degenerate pairs n={n} S={S} volume={want_cost}")
+    ctx, pat = _ctx(bsm, orc, n, S)
+    pairs = [(synth.random_image(500 + i, W, H), synth.random_image(600 + i, W, H), d)
+             for i, (W, H, d) in enumerate(sizes)]
+    items = [(_dev(torch, L), _dev(torch, R), d) for L, R, d in pairs]
+    outs = ctx.match_batch(items, want_cost=want_cost)
+    torch.cuda.synchronize()
+    for (L, R, d), (disp, cost) in zip(pairs, outs):
+        wd, wc = orc.match(L, R, pat, d, want_cost=want_cost)
+        assert np.array_equal(disp.cpu().numpy(), wd), (L.shape, d)
+        if want_cost:
+            assert np.array_equal(cost.cpu().numpy(), wc), (L.shape, d)
+    ctx.close()
+
+
+def test_empty_batch(torch_cuda, bsm, orc):
+    ctx, _ = _ctx(bsm, orc, 256, 15)
+    assert ctx.match_batch([]) == []
+    lib = bsm.load()
+    assert lib.bsm_match_batch(ctx.h, None, 0, None) == bsm.OK
+    assert lib.bsm_autotune(ctx.h, None, 0, 1, None, None, None) == bsm.EINVAL
+    ctx.close()
+
+
 def test_batch_sequential_fallback(torch_cuda, bsm, orc):
     _say("case: batch with n=192 (runs pair by pair)")
     ctx, pat = _ctx(bsm, orc, 192, 11)
