@@ -930,6 +930,10 @@ typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
 
 constexpr int kMfmaTX = 32;     // left pixels per wave
+// Row pitch (int16) of a wave's volume slab [d][pixel]: an odd number of
+// dwords, so the 32 lanes of a half, which write 32 consecutive disparities
+// of one pixel, hit 32 different LDS banks (a 32-entry pitch put them on 4).
+constexpr int kSlabPitch = kMfmaTX + 2;
 constexpr int kMfmaWaves = 4;   // tiles (waves) per workgroup, consecutive in a row
 
 // The 2 NW 32-bit slices of one string (NW 64-bit words at p).
@@ -1052,7 +1056,7 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
       for (int e = 0; e < 16; ++e) {
         const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
         if (d >= 0 && d < dmax)
-          slab[d * kMfmaTX + 8 * (e / 4) + 4 * h + (e % 4)] = static_cast<int16_t>(
+          slab[d * kSlabPitch + 8 * (e / 4) + 4 * h + (e % 4)] = static_cast<int16_t>(
               rb >= 0 ? cbase[e] + (acc[e] >> 3) : kInvalidCost);
       }
     }
@@ -1095,7 +1099,7 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
     // four rows per pass: lane l takes row 4k + l / 16, pixels 2 (l % 16), + 1
     const int pr = lane >> 4, px = 2 * (lane & 15), u = u0 + px;
     for (int d = pr; d < dmax; d += 4) {
-      const uint32_t two = *reinterpret_cast<const uint32_t *>(slab + d * kMfmaTX + px);
+      const uint32_t two = *reinterpret_cast<const uint32_t *>(slab + d * kSlabPitch + px);
       int16_t *dst = cost + ((size_t)d * H + v) * W + u;
       if (u + 1 < W && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
         *reinterpret_cast<uint32_t *>(dst) = two;
@@ -1137,7 +1141,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
   const int tile = (slot % groups) * kMfmaWaves + wave;
   if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
   cost_tile_mfma<NW, MASK, true>(descL, maskL, descR, W, H, dmax, disp, cost,
-                                 slabs + (size_t)wave * dmax * kMfmaTX, v, tile * kMfmaTX);
+                                 slabs + (size_t)wave * dmax * kSlabPitch, v, tile * kMfmaTX);
 }
 
 // ===========================================================================
@@ -1759,7 +1763,7 @@ hipError_t launch_cost_mfma(const uint64_t *descL, const uint64_t *maskL, const 
         allow_big_lds(reinterpret_cast<const void *>(k_cost_wta_mfma_vol<NW, true>))};
     if (attr[0] != hipSuccess) return attr[0];
     if (attr[1] != hipSuccess) return attr[1];
-    const size_t lds = (size_t)kMfmaWaves * dmax * kMfmaTX * sizeof(int16_t);
+    const size_t lds = (size_t)kMfmaWaves * dmax * kSlabPitch * sizeof(int16_t);
     if (maskL)
       hipLaunchKernelGGL((k_cost_wta_mfma_vol<NW, true>), grid, dim3(64 * kMfmaWaves), lds, s,
                          descL, maskL, descR, W, H, dmax, disp, cost);
