@@ -362,11 +362,12 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
   }
   Tuning best_t = ctx->dt.tune;
   double best_time = -1;
-  // Candidates: describe tile width x height x cost window (only when a
-  // pair has a volume: it is the bitwise kernel's) x cost persistent
-  // occupancy x share of the describe workgroups that start on the
-  // descriptor-only tiles.  Each runs on a copy of the tables; the batch
-  // state recaptures its graph whenever the launch choices change.
+  // Candidates: describe tile width x height x share of the describe
+  // workgroups that start on the descriptor-only tiles (one in 3 .. 8) x,
+  // only when a pair has a volume (they are the bitwise kernel's), cost
+  // window and cost persistent occupancy.  Each runs on a copy of the
+  // tables; the batch state recaptures its graph whenever the launch
+  // choices change.
   bool any_volume = false;
   for (int i = 0; i < npairs; ++i) any_volume = any_volume || pairs[i].cost != nullptr;
   std::vector<Tuning> candidates;
@@ -374,8 +375,8 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
     for (int th : {8, 16})
       for (int dc : {32, 64})
         for (int cost_bpc : {0, 2})
-          for (int right_every : {4, 8}) {
-            if (dc == 32 && !any_volume) continue;
+          for (int right_every : {3, 4, 5, 6, 8}) {
+            if (!any_volume && (dc == 32 || cost_bpc == 2)) continue;
             Tuning t;
             t.desc_tile_w = tw;
             t.batch_tile_h = th;
