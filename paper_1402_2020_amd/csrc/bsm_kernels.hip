@@ -550,6 +550,36 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
   const int2 *__restrict__ offs = c.offs;
   if constexpr (PX == 1) {
     uint64_t *out = desc + ((size_t)v * W + px0) * nw;
+    if (nw % kRightGroup == 0) {
+      // Whole groups (n a multiple of 1024): word indices are compile-time
+      // constants and no word is skipped, so the 32 accumulators stay in
+      // registers and leave as eight 16-byte stores.
+      for (int g0 = 0; g0 < nw; g0 += kRightGroup) {
+        uint32_t acc[kRightGroup][2];
+        for_words<kRightGroup>([&](auto J) {
+          constexpr int jj = J.value;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            acc[jj][h] = 0;
+#pragma unroll 8
+            for (int b = 31; b >= 0; --b) {
+              const int2 o = offs[64 * (g0 + jj) + 32 * h + b];  // uniform: scalar load
+              const uint32_t diff =
+                  tile_bytes<1>(itile, base, o.y) - tile_bytes<1>(itile, base, o.x);
+              acc[jj][h] = __builtin_amdgcn_alignbit(acc[jj][h], diff, 31);
+            }
+          }
+        });
+        if (px0 < W) {
+          for_words<kRightGroup / 2>([&](auto K) {
+            constexpr int jj = 2 * K.value;
+            *reinterpret_cast<uint4 *>(out + g0 + jj) =
+                make_uint4(acc[jj][0], acc[jj][1], acc[jj + 1][0], acc[jj + 1][1]);
+          });
+        }
+      }
+      return;
+    }
     for (int g0 = 0; g0 < nw; g0 += kRightGroup) {
       uint32_t acc[kRightGroup][2];
 #pragma unroll
