@@ -6,7 +6,10 @@ The right-reference matcher is written from its own definition (right view
 as reference, partner (u + d, v) in the left view, the right view's mask);
 it is pinned to the independently pinned left-reference matcher through the
 mirror identity, to brute force on tiny images and to exact recovery of a
-constant disparity.  The check is pinned to a direct Python loop.
+constant disparity.  The check is pinned to scene geometry: on layered
+fronto-parallel scenes it must reject exactly the left pixels whose partner
+shows another surface (the occlusion band left of a nearer surface, the
+left border), which a wrong partner column such as u + d cannot reproduce.
 """
 import numpy as np
 import pytest
@@ -106,3 +109,66 @@ def test_lr_check_of_consistent_maps(orc):
     inner = chk[r:20 - r, d0 + r:48 - r]
     assert np.mean(inner == d0) > 0.9
     assert np.all((chk == -1) | (chk == dl))
+
+
+def _render_layers(W, H, layers):
+    """Ground truth of a scene of fronto-parallel layers (x0, y0, w, h, d),
+    given in left-view coordinates on a canvas wider than the image; a nearer
+    layer (larger d) hides a farther one.  Returns the integer disparity maps
+    of both views and the layer each pixel shows.  The right pixel ur shows
+    the left position ur + d of a layer (Section 3: x_d = (u - d, v))."""
+    dl = np.zeros((H, W), np.int32)
+    dr = np.zeros((H, W), np.int32)
+    sl = np.full((H, W), -1)
+    sr = np.full((H, W), -1)
+    for k, (x0, y0, w, h, d) in enumerate(layers):
+        for v in range(max(0, y0), min(H, y0 + h)):
+            for u in range(W):
+                if x0 <= u < x0 + w and (sl[v, u] < 0 or d > dl[v, u]):
+                    dl[v, u], sl[v, u] = d, k
+                if x0 <= u + d < x0 + w and (sr[v, u] < 0 or d > dr[v, u]):
+                    dr[v, u], sr[v, u] = d, k
+    return dl, dr, sl, sr
+
+
+def _occluded(dl, sl, sr):
+    """Left pixels whose partner (u - d, v) lies outside the right view or
+    shows another surface: what the left/right check must reject."""
+    H, W = dl.shape
+    occ = np.zeros((H, W), bool)
+    for v in range(H):
+        for u in range(W):
+            ur = u - dl[v, u]
+            occ[v, u] = ur < 0 or sr[v, ur] != sl[v, u]
+    return occ
+
+
+def test_lr_check_rejects_exactly_the_occlusion_band(orc):
+    # A background at d = 3 and a full-height foreground strip at d = 9 over
+    # left columns [30, 45): the background is hidden in the right view for
+    # the 9 - 3 = 6 columns just left of the strip, [24, 30), and the left
+    # border columns u < 3 have no partner.  Nothing else may be rejected.
+    W, H = 64, 5
+    dl, dr, sl, sr = _render_layers(W, H, [(0, 0, 200, H, 3), (30, 0, 15, H, 9)])
+    want_invalid = np.zeros((H, W), bool)
+    want_invalid[:, :3] = True
+    want_invalid[:, 24:30] = True
+    assert np.array_equal(_occluded(dl, sl, sr), want_invalid)   # the geometry itself
+    for tol in (0, 1, 5):
+        chk = orc.lr_check(dl, dr, tol=tol)
+        assert np.array_equal(chk < 0, want_invalid), tol
+        assert np.array_equal(chk[~want_invalid], dl[~want_invalid])
+
+
+def test_lr_check_rejects_exactly_the_occluded_pixels_of_the_rectangle_scene(orc):
+    # The layers of the 128x96 rectangle workload (distinct integer
+    # disparities, at least 1 apart): with tol = 0 the check keeps a left
+    # pixel exactly when its partner shows the same surface.
+    sc = synth.rect_scene(14022020, 128, 96, 16)
+    dl, dr, sl, sr = _render_layers(128, 96, sc.meta["layers"])
+    assert np.array_equal(dl, sc.gt.astype(np.int32))
+    occ = _occluded(dl, sl, sr)
+    assert 0 < occ.sum() < occ.size // 4
+    chk = orc.lr_check(dl, dr, tol=0)
+    assert np.array_equal(chk < 0, occ)
+    assert np.array_equal(chk[~occ], dl[~occ])
