@@ -31,7 +31,8 @@ MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix o
 
 def cost_on_matrix_cores(tuning, n, dmax, want_cost):
     """Whether bsm_cost_wta takes the matrix-core kernel (the library's rule)."""
-    return (tuning.get("cost_mfma", 1) == 1 and n // 64 in (1, 2, 4, 8, 16) and dmax > 16
+    return (tuning.get("cost_mfma", 1) == 1 and n // 64 in (1, 2, 4, 8, 16)
+            and dmax >= tuning.get("mfma_min_dmax", 17)
             and (not want_cost or dmax <= 256))
 
 WORKLOADS = {
@@ -58,10 +59,68 @@ RADIOMETRIC = [  # name, gain, gamma, per-channel offset
 ]
 
 
+def _gen_batch_scene(args):
+    from paper_1402_2020_amd import synth
+    spec, scale = args
+    return synth.batch_scene(spec, scale=scale)
+
+
+def batch_scenes(specs, scale=1.0):
+    """The uneven pairs, generated in parallel on the host cores (about a
+    second per full-size pair on one core)."""
+    import concurrent.futures as cf
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(specs)))
+    if workers == 1:
+        return [_gen_batch_scene((s, scale)) for s in specs]
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_gen_batch_scene, [(s, scale) for s in specs]))
+
+
+def batch_cpu_baseline(scenes, pat, n, budget_s=10.0):
+    """The oracle (as it stands) on a bounded sample of the batch: whole
+    pairs in batch order on all host cores until about budget_s seconds, and
+    the smallest pair once on one pinned core."""
+    import oracle
+    cores = sorted(os.sched_getaffinity(0))
+    threads = len(cores)
+    oracle.set_threads(threads)
+    evals, t, used = 0, 0.0, 0
+    for sc in scenes:
+        t0 = time.perf_counter()
+        oracle.match(sc.left, sc.right, pat, sc.dmax)
+        t += time.perf_counter() - t0
+        H, W = sc.left.shape[:2]
+        evals += W * H * sc.dmax
+        used += 1
+        if t >= budget_s:
+            break
+    out = {"value": evals / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "seconds": round(t, 3),
+           "sample": f"the first {used} of the {len(scenes)} batch pairs ({evals / 1e9:.3f} G "
+                     f"evaluations), whole pipeline per pair, {threads} OpenMP threads over rows"}
+    small = min(scenes, key=lambda sc: sc.left.shape[0] * sc.left.shape[1] * sc.dmax)
+    H, W = small.left.shape[:2]
+    oracle.set_threads(1)
+    try:
+        os.sched_setaffinity(0, {cores[0]})
+        t0 = time.perf_counter()
+        oracle.match(small.left, small.right, pat, small.dmax)
+        t1 = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(cores))
+    out["single_core"] = {"value": W * H * small.dmax / t1, "unit": "evals/s", "cores": 1,
+                          "seconds": round(t1, 3),
+                          "sample": f"the smallest batch pair ({W}x{H}, dmax {small.dmax}) "
+                                    f"once, one thread pinned to core {cores[0]}"}
+    return out
+
+
 def bench_batch(args):
     """The uneven 64-pair batch: one bsm_match_batch call (persistent stage
     kernels replayed from a HIP graph, autotuned first) per step, against
-    64 plain bsm_match calls on the same pairs."""
+    64 plain bsm_match calls on the same pairs.  The roofline is the
+    dominant stage's, timed with HIP events between eagerly launched stages
+    (bsm_batch_stage_times) on the same stream."""
     import torch
 
     from paper_1402_2020_amd import _bsm, synth
@@ -69,15 +128,20 @@ def bench_batch(args):
     sigma = 4.0 * S / 26
     specs = synth.batch_specs(64)
     t0 = time.perf_counter()
-    scenes = [synth.batch_scene(s) for s in specs]
+    scenes = batch_scenes(specs)
     gen_s = time.perf_counter() - t0
+    print(json.dumps({"progress": "scenes", "pairs": len(scenes), "seconds": round(gen_s, 1)}),
+          flush=True)
     pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
     ctx = _bsm.Context(n, S, sigma, pattern=pat, device=0)
     dev = torch.device("cuda:0")
     items = [(torch.from_numpy(s.left).to(dev), torch.from_numpy(s.right).to(dev), s.dmax)
              for s in scenes]
     evals = sum(s.left.shape[0] * s.left.shape[1] * s.dmax for s in scenes)
-    best, tune_ms = ctx.autotune(items, reps=2)
+    pixels = sum(s.left.shape[0] * s.left.shape[1] for s in scenes)
+    best, tune_ms, hit = ctx.autotune_cached(items, args.tuning_cache, reps=2)
+    print(json.dumps({"progress": "tuning", "from_cache": hit, "tuning": best,
+                      "ms": round(tune_ms, 3)}), flush=True)
     stream = torch.cuda.current_stream()
     pairs, outs, keep = ctx._pairs(items, False)
     lib = _bsm.load()
@@ -106,18 +170,60 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
-    steps = max(1, min(args.steps, 20))
-    ms_batch = timed(batch_step, steps, max(1, args.warmup))
+    steps = max(1, min(args.steps, 50))
+    warmup = max(1, args.warmup)
+    ms_batch = timed(batch_step, steps, warmup)
     batch_disp = [o[0].clone() for o in outs]
+    print(json.dumps({"progress": "batch", "ms_per_step": round(ms_batch, 3)}), flush=True)
     ms_plain = timed(plain_step, steps, 1)
     same = all(torch.equal(a, o[0]) for a, o in zip(batch_disp, outs))
+    print(json.dumps({"progress": "plain", "ms_per_step": round(ms_plain, 3)}), flush=True)
+
+    # Stage times: the same batch with its stages launched eagerly and HIP
+    # events between them, averaged over the timed steps.
+    stage_names = ["batch_color", "batch_describe", "batch_cost", "batch_cost_volume"]
+    acc = [0.0] * 4
+    for _ in range(steps):
+        st, ms = _bsm.bsm_batch_stage_times(ctx.h, pairs, sp)
+        if st != 0:
+            raise RuntimeError(_bsm.bsm_last_error())
+        acc = [a + m for a, m in zip(acc, ms)]
+    stage_ms = {k: a / steps for k, a in zip(stage_names, acc)}
+    same = same and all(torch.equal(a, o[0]) for a, o in zip(batch_disp, outs))
+    # algorithmic work of each stage per batch
+    work = {
+        # per pixel: the left view's descriptor + mask (15 n lane-ops: tau,
+        # two SADs, max, ~10 threshold-search compares and delta per pair)
+        # and the right view's descriptor (n: tau per pair)
+        "batch_describe": ("alu", pixels * 16 * n, ALU_PEAK_OPS, "TOP/s", 1e12),
+        # per evaluation an n-bit int8 dot product on the matrix cores (2 n ops)
+        "batch_cost": ("mfma", evals * 2 * n, MFMA_I8_PEAK_OPS, "TOP/s", 1e12),
+        # per pixel and view: 3 B of RGB in, 4 B of packed colour out
+        "batch_color": ("hbm", pixels * 2 * 7, HBM_PEAK_BPS, "GB/s", 1e9),
+    }
+    kernels = {}
+    for name, ms in stage_ms.items():
+        ent = {"ms": round(ms, 4)}
+        if name in work and ms > 0:
+            bound, amount, peak, unit, scale = work[name]
+            ent.update(bound=bound, achieved=round(amount / (ms / 1e3) / scale, 3), unit=unit,
+                       frac=round(amount / (ms / 1e3) / peak, 4))
+        kernels[name] = ent
+    kernels["batch_cost"]["valu_popcount_equiv_frac"] = round(
+        evals * (n // 16 + 1) / (stage_ms["batch_cost"] / 1e3) / ALU_PEAK_OPS, 4)
+    dom = max((k for k in stage_ms if k in work), key=lambda k: stage_ms[k])
+    bound, amount, peak, unit, scale = work[dom]
+    dms = stage_ms[dom]
+    roof = {"kernel": dom, "bound": bound, "achieved": round(amount / (dms / 1e3) / scale, 3),
+            "peak": round(peak / scale, 2), "unit": unit,
+            "frac": round(amount / (dms / 1e3) / peak, 4), "traffic": traffic_for(dom, 3)}
     out = {
         "metric": "disparity evals/sec (W*H*dmax/s)",
         "value": evals / (ms_batch / 1e3),
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": max(1, args.warmup),
+        "warmup": warmup,
         "ms_per_step": ms_batch,
         "higher_is_better": True,
         "scaling": "weak",
@@ -125,21 +231,23 @@ def bench_batch(args):
         "dtype": "u64",
         "data": "synthetic (seeded scene generator; Middlebury stand-in)",
         "config": {"workload": WORKLOADS[3], "pairs_per_step": len(scenes),
-                   "total_evals": evals, "n_bits": n, "window": S},
+                   "total_evals": evals, "total_pixels": pixels, "n_bits": n, "window": S},
         "pairs_per_s": len(scenes) / (ms_batch / 1e3),
         "plain": {"ms_per_step": ms_plain, "pairs_per_s": len(scenes) / (ms_plain / 1e3),
                   "evals_per_s": evals / (ms_plain / 1e3)},
         "batch_speedup_vs_plain": ms_plain / ms_batch,
         "batch_equals_plain": bool(same),
         "tuning": best,
+        "tuning_from_cache": hit,
         "autotune_best_ms": tune_ms,
         "scene_generation_s": round(gen_s, 2),
-        "roofline": None,
+        "kernels": kernels,
+        "roofline": roof,
     }
     # The same 64 pairs at a quarter of the size (W 80-480, H 60-270, dmax
     # 8-64): launch-bound pairs, where one persistent launch for all of them
     # pays off.  Reported beside, not as the value.
-    small = [synth.batch_scene(s, scale=0.25) for s in specs]
+    small = batch_scenes(specs, scale=0.25)
     s_items = [(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), sc.dmax)
                for sc in small]
     s_pairs, s_outs, s_keep = ctx._pairs(s_items, False)
@@ -155,7 +263,7 @@ def bench_batch(args):
                              None, sp) != 0:
                 raise RuntimeError(_bsm.bsm_last_error())
 
-    ms_sb = timed(small_batch, steps, max(1, args.warmup))
+    ms_sb = timed(small_batch, steps, warmup)
     s_disp = [o[0].clone() for o in s_outs]
     ms_sp = timed(small_plain, steps, 1)
     out["quarter_size_pairs"] = {
@@ -165,6 +273,10 @@ def bench_batch(args):
         "batch_equals_plain": all(torch.equal(a, o[0]) for a, o in zip(s_disp, s_outs)),
     }
     ctx.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        opat = oracle.make_pattern(synth.PATTERN_SEED, n, S, sigma)
+        out["cpu_baseline"] = batch_cpu_baseline(scenes, opat, n)
     print(json.dumps(out), flush=True)
 
 
@@ -509,8 +621,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
+    ap.add_argument("--config", type=int, default=3, choices=sorted(WORKLOADS),
+                    help="workload (default 3: the 64 uneven pairs, the largest one-GPU "
+                         "workload); 0-2 single pairs, 4 serving, 5 n-sweep, 6 radiometric")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_1402_2020_amd",
+                                                           "tuning_cache.json"),
+                    help="batch workload: the autotuner's persistent cache (a hit skips the "
+                         "search)")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serving workload: seconds of arrivals per rate")
     ap.add_argument("--rates", type=int, nargs="+", default=[50, 200, 800],

@@ -220,9 +220,11 @@ bsm_status bsm_lr_check(bsm_ctx *ctx, const int32_t *disp_left,
  * window and the colour space open, this library takes the matching window
  * and CIELAB).  Ties take the lowest d; an invalid pixel without voters
  * takes fallback(x) (e.g. the WTA disparity); valid pixels keep checked(x).
- * Votes are summed in fp32.  left: device RGB; checked, fallback, out:
- * device int32 [H][W], 4-byte aligned; out may be fallback but not
- * checked.  1 <= dmax <= 4096, 0 <= radius <= 63.  Uses context scratch. */
+ * Votes are summed in fp32 in a fixed order: the same result on every
+ * run, which may differ from an exact sum only at near-ties.  left: device
+ * RGB; checked, fallback, out: device int32 [H][W], 4-byte aligned; out may
+ * be fallback but not checked.  1 <= dmax <= 4096, 0 <= radius <= 63.
+ * Uses context scratch. */
 bsm_status bsm_vote_refine(bsm_ctx *ctx, const uint8_t *left, int32_t W,
                            int32_t H, int32_t stride, const int32_t *checked,
                            const int32_t *fallback, int32_t dmax,
@@ -261,8 +263,18 @@ typedef struct {
                                  volume; single pairs, and batch pairs
                                  without one); 0: the bitwise VALU kernel */
     int32_t batch_tile_h;     /* describe+mask tile height of the persistent
-                                 batch: 8 or 16 rows (default 16; single
-                                 pairs choose their own)                    */
+                                 batch: 8 or 16 rows (default 16)           */
+    int32_t pair_desc_th;     /* single pairs (and batches of up to four):
+                                 describe+mask tile height, 4 or 8 rows;
+                                 0 (default): 4 below 4096 tiles of 8 rows,
+                                 else 8                                     */
+    int32_t pair_right_px;    /* single pairs: pixels per lane of the
+                                 descriptor-only kernel, 1 or 4; 0
+                                 (default): 4 from 1024 tiles of 4 x 256
+                                 pixels on, else 1                          */
+    int32_t mfma_min_dmax;    /* smallest dmax that takes the matrix-core
+                                 cost kernel when cost_mfma = 1, 2..257
+                                 (default 17)                               */
 } bsm_tuning;
 
 bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out);
@@ -271,12 +283,49 @@ bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *tuning);
 
 /* Autotuner: times bsm_match_batch on `pairs` (device pointers, as for
  * bsm_match_batch; outputs are overwritten) for each candidate tuning,
- * `reps` timed runs each, keeps the fastest on the context and returns it
- * in *best with its mean time per batch in *best_ms (either may be NULL).
- * Blocks until done. */
+ * `reps` timed runs each after one untimed run, keeps the fastest on the
+ * context and returns it in *best with its mean time per batch in *best_ms
+ * (either may be NULL).  Blocks until done.  Candidates for the persistent
+ * batch: desc_tile_w 16/32 x batch_tile_h 8/16 x blocks_per_cu[2] (the
+ * describe split) 3/4/5/6/8, and, when a pair has a volume, cost_dchunk
+ * 32/64 x blocks_per_cu[3] 0/2.  For pairs that run one by one (a single
+ * pair, or up to four): desc_tile_w 16/32 x pair_desc_th 4/8 x
+ * pair_right_px 1/4 x cost_mfma 1/0 (0 only where the matrix-core kernel
+ * applies). */
 bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t npairs,
                         int32_t reps, void *hip_stream, bsm_tuning *best,
                         double *best_ms);
+
+/* Autotuner with a persistent cache.  cache_path names a JSON file (one
+ * object, one entry per line) mapping a key to a tuning and its time.  The
+ * key holds the GPU architecture, n, S, the mask mode and the shape class
+ * of `pairs`: the path they take ("batch" or "pairs"), the pair count, the
+ * largest dmax and the mean pixel count in thousands (each rounded up to a
+ * power of two) and whether a volume is wanted.  If the file holds the key,
+ * its tuning is set on the context without running anything and *hit = 1;
+ * otherwise bsm_autotune runs, its winner is added to the file (written to
+ * cache_path.tmp, then renamed) and *hit = 0.  cache_path NULL: no cache.
+ * best, best_ms, hit may be NULL.  BSM_EINVAL if the file cannot be
+ * written (the context keeps the tuned choice). */
+bsm_status bsm_autotune_cached(bsm_ctx *ctx, const bsm_pair *pairs,
+                               int32_t npairs, int32_t reps,
+                               void *hip_stream, const char *cache_path,
+                               bsm_tuning *best, double *best_ms,
+                               int32_t *hit);
+
+/* Measurement of a batch's stages: runs `pairs` like bsm_match_batch (same
+ * work list, kernels and results) but launches the stage kernels directly
+ * on the stream instead of replaying the graph, with HIP events between
+ * them; waits for the batch and writes each stage's time in milliseconds
+ * to the host array stage_ms[4]: [0] colour pre-pass of all views,
+ * [1] both describe stages (descriptor + mask of the left views,
+ * descriptor of the right views, one launch), [2] cost + WTA of the pairs
+ * without a volume, [3] of the pairs with one.  Needs the persistent path
+ * (n in {64, 128, 256, 512, 1024} and at least five pairs), else
+ * BSM_EINVAL. */
+bsm_status bsm_batch_stage_times(bsm_ctx *ctx, const bsm_pair *pairs,
+                                 int32_t npairs, void *hip_stream,
+                                 float *stage_ms);
 
 /* Serving: admission cap on the device working set of pairs in flight
  * (bytes; default 32 GiB), the maximum number of queued requests (default

@@ -20,7 +20,8 @@ INVALID_COST = 32767
 EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
            "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
            "bsm_match_right", "bsm_lr_check", "bsm_vote_refine",
-           "bsm_match_batch", "bsm_get_tuning", "bsm_set_tuning", "bsm_autotune",
+           "bsm_match_batch", "bsm_batch_stage_times", "bsm_get_tuning", "bsm_set_tuning",
+           "bsm_autotune", "bsm_autotune_cached",
            "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain", "bsm_serve_stats")
 
 
@@ -59,12 +60,14 @@ class ServeCounters(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("desc_tile_w", C.c_int32), ("cost_dchunk", C.c_int32),
                 ("blocks_per_cu", C.c_int32 * 4), ("cost_mfma", C.c_int32),
-                ("batch_tile_h", C.c_int32)]
+                ("batch_tile_h", C.c_int32), ("pair_desc_th", C.c_int32),
+                ("pair_right_px", C.c_int32), ("mfma_min_dmax", C.c_int32)]
 
     def as_dict(self):
         return {"desc_tile_w": self.desc_tile_w, "cost_dchunk": self.cost_dchunk,
                 "blocks_per_cu": list(self.blocks_per_cu), "cost_mfma": self.cost_mfma,
-                "batch_tile_h": self.batch_tile_h}
+                "batch_tile_h": self.batch_tile_h, "pair_desc_th": self.pair_desc_th,
+                "pair_right_px": self.pair_right_px, "mfma_min_dmax": self.mfma_min_dmax}
 
     @classmethod
     def from_dict(cls, d):
@@ -75,6 +78,9 @@ class Tuning(C.Structure):
             t.blocks_per_cu[i] = int(v)
         t.cost_mfma = int(d.get("cost_mfma", 1))
         t.batch_tile_h = int(d.get("batch_tile_h", 16))
+        t.pair_desc_th = int(d.get("pair_desc_th", 0))
+        t.pair_right_px = int(d.get("pair_right_px", 0))
+        t.mfma_min_dmax = int(d.get("mfma_min_dmax", 17))
         return t
 
 
@@ -109,10 +115,13 @@ def load():
         "bsm_vote_refine": ([vp, vp, i32, i32, i32, vp, vp, i32, i32, C.c_float, C.c_float, vp, vp],
                             st),
         "bsm_match_batch": ([vp, C.POINTER(Pair), i32, vp], st),
+        "bsm_batch_stage_times": ([vp, C.POINTER(Pair), i32, vp, C.POINTER(C.c_float)], st),
         "bsm_get_tuning": ([vp, C.POINTER(Tuning)], st),
         "bsm_set_tuning": ([vp, C.POINTER(Tuning)], st),
         "bsm_autotune": ([vp, C.POINTER(Pair), i32, i32, vp, C.POINTER(Tuning),
                           C.POINTER(C.c_double)], st),
+        "bsm_autotune_cached": ([vp, C.POINTER(Pair), i32, i32, vp, C.c_char_p,
+                                 C.POINTER(Tuning), C.POINTER(C.c_double), C.POINTER(i32)], st),
         "bsm_serve_config": ([vp, sz, i32, i32], st),
         "bsm_serve_stats": ([vp, C.POINTER(ServeCounters)], st),
         "bsm_submit": ([vp, C.POINTER(Pair), C.POINTER(u64)], st),
@@ -223,12 +232,31 @@ def bsm_set_tuning(ctx, tuning):
     return load().bsm_set_tuning(ctx, C.byref(tuning))
 
 
+def bsm_batch_stage_times(ctx, pairs, stream):
+    """Returns (status, [colour, describe, cost, cost with volume] ms)."""
+    arr = (Pair * len(pairs))(*pairs)
+    ms = (C.c_float * 4)()
+    st = load().bsm_batch_stage_times(ctx, arr, len(pairs), stream, ms)
+    return st, list(ms)
+
+
 def bsm_autotune(ctx, pairs, reps, stream):
     arr = (Pair * len(pairs))(*pairs)
     best = Tuning()
     ms = C.c_double()
     st = load().bsm_autotune(ctx, arr, len(pairs), reps, stream, C.byref(best), C.byref(ms))
     return st, best, ms.value
+
+
+def bsm_autotune_cached(ctx, pairs, reps, stream, cache_path):
+    arr = (Pair * len(pairs))(*pairs)
+    best = Tuning()
+    ms = C.c_double()
+    hit = C.c_int32()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    st = load().bsm_autotune_cached(ctx, arr, len(pairs), reps, stream, path, C.byref(best),
+                                    C.byref(ms), C.byref(hit))
+    return st, best, ms.value, bool(hit.value)
 
 
 def bsm_serve_config(ctx, cap_bytes, max_queue, max_group=0):
@@ -413,6 +441,15 @@ class Context:
         _check(st, "bsm_autotune")
         del keep
         return best.as_dict(), ms
+
+    def autotune_cached(self, items, cache_path, reps=3, stream=None, want_cost=False):
+        """As autotune, through the persistent cache at cache_path; returns
+        (tuning dict, ms, hit)."""
+        pairs, _, keep = self._pairs(items, want_cost)
+        st, best, ms, hit = bsm_autotune_cached(self.h, pairs, reps, _stream(stream), cache_path)
+        _check(st, "bsm_autotune_cached")
+        del keep
+        return best.as_dict(), ms, hit
 
     def _pairs(self, items, want_cost):
         import torch

@@ -8,8 +8,11 @@
 // list travels host -> device through a pinned staging buffer just before
 // the graph launch, on the same stream.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <numeric>
+#include <sstream>
 #include <vector>
 
 #include "bsm_internal.h"
@@ -141,8 +144,11 @@ bool same_tuning(const Tuning &a, const Tuning &b) {
   return true;
 }
 
+// marks != nullptr: the stages are launched directly on s with the events
+// recorded between them (the graph is neither used nor captured).
 bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
-                            const bsm_pair *pairs, int npairs, hipStream_t s) {
+                            const bsm_pair *pairs, int npairs, hipStream_t s,
+                            const hipEvent_t *marks = nullptr) {
   const int use_mask = ctx->use_mask;
   hipError_t e;
 
@@ -254,28 +260,34 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
     return device_fail(ctx, e, "uploading the batch work list");
   if ((e = hipEventRecord(b.staged, s)) != hipSuccess) return device_fail(ctx, e, "batch event");
 
-  const BatchLaunch bl{b.d_work, b.d_counters};
-  if (!b.exec) {
-    // Capture the stage launches once; they read everything else from the
-    // work list, so the graph serves every later batch of this context.
-    if ((e = hipStreamBeginCapture(b.capture, hipStreamCaptureModeRelaxed)) != hipSuccess)
-      return device_fail(ctx, e, "beginning batch graph capture");
-    hipError_t le = launch_batch(bl, dt, use_mask, b.capture);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b.capture, &g);
-    if (le != hipSuccess || e != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return device_fail(ctx, le != hipSuccess ? le : e, "capturing the batch graph");
+  if (marks) {
+    const BatchLaunch bl{b.d_work, b.d_counters, marks};
+    if ((e = launch_batch(bl, dt, use_mask, s)) != hipSuccess)
+      return device_fail(ctx, e, "launching the batch stages");
+  } else {
+    const BatchLaunch bl{b.d_work, b.d_counters};
+    if (!b.exec) {
+      // Capture the stage launches once; they read everything else from the
+      // work list, so the graph serves every later batch of this context.
+      if ((e = hipStreamBeginCapture(b.capture, hipStreamCaptureModeRelaxed)) != hipSuccess)
+        return device_fail(ctx, e, "beginning batch graph capture");
+      hipError_t le = launch_batch(bl, dt, use_mask, b.capture);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(b.capture, &g);
+      if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return device_fail(ctx, le != hipSuccess ? le : e, "capturing the batch graph");
+      }
+      b.graph = g;
+      if ((e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0)) != hipSuccess) {
+        b.drop_graph();
+        return device_fail(ctx, e, "instantiating the batch graph");
+      }
+      b.tune = dt.tune;
     }
-    b.graph = g;
-    if ((e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0)) != hipSuccess) {
-      b.drop_graph();
-      return device_fail(ctx, e, "instantiating the batch graph");
-    }
-    b.tune = dt.tune;
+    if ((e = hipGraphLaunch(b.exec, s)) != hipSuccess)
+      return device_fail(ctx, e, "launching the batch graph");
   }
-  if ((e = hipGraphLaunch(b.exec, s)) != hipSuccess)
-    return device_fail(ctx, e, "launching the batch graph");
   if ((e = hipEventRecord(b.done, s)) != hipSuccess) return device_fail(ctx, e, "batch event");
   b.launched = true;
   b.last_stream = s;
@@ -284,6 +296,15 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
 }
 
 }  // namespace
+
+bsm_status batch_run_marked(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
+                            const bsm_pair *pairs, int npairs, hipStream_t s,
+                            const hipEvent_t *marks) {
+  if (!batch_supported(ctx->nw) || npairs <= kSequentialMaxPairs)
+    return fail(BSM_EINVAL, "stage times need the persistent path (n in {64, 128, 256, 512, "
+                            "1024} and more than %d pairs)", kSequentialMaxPairs);
+  return batch_persistent(ctx, b, dt, pairs, npairs, s, marks);
+}
 
 bsm_status batch_run(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt, const bsm_pair *pairs,
                      int npairs, hipStream_t s) {
@@ -341,6 +362,233 @@ extern "C" bsm_status bsm_match_batch(bsm_ctx *ctx, const bsm_pair *pairs, int32
   return run_batch(ctx, pairs, npairs, static_cast<hipStream_t>(hip_stream));
 }
 
+extern "C" bsm_status bsm_batch_stage_times(bsm_ctx *ctx, const bsm_pair *pairs,
+                                            int32_t npairs, void *hip_stream,
+                                            float *stage_ms) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_pairs(pairs, npairs)) != BSM_OK) return st;
+  if (!stage_ms) return fail(BSM_EINVAL, "stage_ms is NULL");
+  OnDevice g(ctx->device);
+  if (g.err != hipSuccess) return device_fail(ctx, g.err, "hipSetDevice");
+  if ((st = ensure_batch_state(ctx)) != BSM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t ev[kBatchMarks] = {};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kBatchMarks && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  if (e == hipSuccess) {
+    st = batch_run_marked(ctx, *ctx->batch, ctx->dt, pairs, npairs, s, ev);
+    if (st == BSM_OK) e = hipEventSynchronize(ev[kBatchMarks - 1]);
+    for (int i = 0; i < kBatchStages && st == BSM_OK && e == hipSuccess; ++i)
+      e = hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]);
+  }
+  for (int i = 0; i < kBatchMarks; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  if (st != BSM_OK) return st;
+  if (e != hipSuccess) return device_fail(ctx, e, "batch stage events");
+  return BSM_OK;
+}
+
+namespace bsm {
+namespace {
+
+bool takes_persistent_path(const bsm_ctx *ctx, int npairs) {
+  return batch_supported(ctx->nw) && npairs > kSequentialMaxPairs;
+}
+
+// Candidate tunings.  The persistent batch: describe tile width x height x
+// share of the describe workgroups that start on the descriptor-only tiles
+// (one in 3 .. 8) and, only when a pair has a volume (they belong to the
+// bitwise kernel), cost window and cost occupancy.  Pairs run one by one
+// (batches of up to four, single pairs): describe tile width x tile height
+// x pixels per lane of the descriptor-only kernel x matrix-core or bitwise
+// cost kernel (the latter only where the matrix-core kernel applies).
+std::vector<Tuning> autotune_candidates(const bsm_ctx *ctx, const bsm_pair *pairs, int npairs) {
+  bool any_volume = false, mfma_possible = false;
+  for (int i = 0; i < npairs; ++i) {
+    any_volume = any_volume || pairs[i].cost != nullptr;
+    mfma_possible = mfma_possible ||
+                    (pairs[i].dmax > 16 && (!pairs[i].cost || pairs[i].dmax <= 256));
+  }
+  std::vector<Tuning> out;
+  if (takes_persistent_path(ctx, npairs)) {
+    for (int tw : {16, 32})
+      for (int th : {8, 16})
+        for (int dc : {32, 64})
+          for (int cost_bpc : {0, 2})
+            for (int right_every : {3, 4, 5, 6, 8}) {
+              if (!any_volume && (dc == 32 || cost_bpc == 2)) continue;
+              Tuning t;
+              t.desc_tile_w = tw;
+              t.batch_tile_h = th;
+              t.cost_dchunk = dc;
+              t.blocks_per_cu[2] = right_every;
+              t.blocks_per_cu[3] = cost_bpc;
+              out.push_back(t);
+            }
+  } else {
+    const bool fast_nw = batch_supported(ctx->nw);
+    for (int tw : {16, 32})
+      for (int th : {4, 8})
+        for (int px : {1, 4})
+          for (int mfma : {1, 0}) {
+            if (mfma == 0 && !(mfma_possible && fast_nw)) continue;
+            Tuning t;
+            t.desc_tile_w = tw;
+            t.pair_desc_th = th;
+            t.pair_right_px = px;
+            t.cost_mfma = mfma;
+            out.push_back(t);
+          }
+  }
+  return out;
+}
+
+// Times every candidate on `pairs` (one untimed run, then `reps` timed
+// runs each) and returns the fastest with its mean time per call.
+bsm_status autotune_search(bsm_ctx *ctx, const bsm_pair *pairs, int npairs, int reps,
+                           hipStream_t s, Tuning *best_t, double *best_time) {
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return device_fail(ctx, e, "autotune events");
+  }
+  bsm_status st = BSM_OK;
+  *best_t = ctx->dt.tune;
+  *best_time = -1;
+  for (const Tuning &cand : autotune_candidates(ctx, pairs, npairs)) {
+    DeviceTables dt = ctx->dt;
+    dt.tune = cand;
+    if ((st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s)) != BSM_OK) break;
+    if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+    for (int r = 0; r < reps && st == BSM_OK; ++r)
+      st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s);
+    if (st != BSM_OK) break;
+    if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
+      break;
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+    const double per = ms / reps;
+    if (*best_time < 0 || per < *best_time) {
+      *best_time = per;
+      *best_t = cand;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st == BSM_OK && e != hipSuccess) st = device_fail(ctx, e, "autotune timing");
+  return st;
+}
+
+void tuning_to_c(const Tuning &t, bsm_tuning *out) {
+  out->desc_tile_w = t.desc_tile_w;
+  out->cost_dchunk = t.cost_dchunk;
+  for (int i = 0; i < 4; ++i) out->blocks_per_cu[i] = t.blocks_per_cu[i];
+  out->cost_mfma = t.cost_mfma;
+  out->batch_tile_h = t.batch_tile_h;
+  out->pair_desc_th = t.pair_desc_th;
+  out->pair_right_px = t.pair_right_px;
+  out->mfma_min_dmax = t.mfma_min_dmax;
+}
+
+void set_context_tuning(bsm_ctx *ctx, const Tuning &t) {
+  std::lock_guard<std::mutex> lk(ctx->tune_mu);
+  ctx->dt.tune = t;
+}
+
+int pow2_at_least(double x) {
+  int p = 1;
+  while (p < x && p < (1 << 30)) p <<= 1;
+  return p;
+}
+
+// Cache key: GPU architecture, n, S, mask mode and the shape class of the
+// pairs (path, pair count, largest dmax, mean pixels in thousands, each
+// rounded up to a power of two, and whether a volume is wanted).
+std::string autotune_key(const bsm_ctx *ctx, const bsm_pair *pairs, int npairs) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  int max_dmax = 1;
+  double px = 0;
+  bool vol = false;
+  for (int i = 0; i < npairs; ++i) {
+    max_dmax = std::max(max_dmax, pairs[i].dmax);
+    px += (double)pairs[i].width * pairs[i].height;
+    vol = vol || pairs[i].cost != nullptr;
+  }
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s n%d S%d mask%d %s pairs%d dmax%d kpx%d vol%d", arch.c_str(),
+           ctx->n, ctx->S, ctx->use_mask, takes_persistent_path(ctx, npairs) ? "batch" : "pairs",
+           pow2_at_least(npairs), pow2_at_least(max_dmax), pow2_at_least(px / npairs / 1000.0),
+           vol ? 1 : 0);
+  return buf;
+}
+
+// The cache file is one JSON object with one entry per line:
+//   "<key>": {"desc_tile_w": 32, ..., "ms": 52.9},
+constexpr const char *kEntryFormat =
+    "{\"desc_tile_w\": %d, \"cost_dchunk\": %d, \"blocks_per_cu\": [%d, %d, %d, %d], "
+    "\"cost_mfma\": %d, \"batch_tile_h\": %d, \"pair_desc_th\": %d, \"pair_right_px\": %d, "
+    "\"mfma_min_dmax\": %d, \"ms\": %lf}";
+
+// Entries of the file as (key, rest of the line); unreadable lines are
+// dropped.
+std::vector<std::pair<std::string, std::string>> cache_read(const char *path) {
+  std::vector<std::pair<std::string, std::string>> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find('"');
+    if (a == std::string::npos) continue;
+    const size_t b = line.find('"', a + 1);
+    const size_t c = line.find('{', b == std::string::npos ? a : b);
+    if (b == std::string::npos || c == std::string::npos) continue;
+    std::string rest = line.substr(c);
+    while (!rest.empty() && (rest.back() == ',' || rest.back() == ' ' || rest.back() == '\r'))
+      rest.pop_back();
+    out.emplace_back(line.substr(a + 1, b - a - 1), rest);
+  }
+  return out;
+}
+
+bool parse_entry(const std::string &text, Tuning *t, double *ms) {
+  Tuning x;
+  const int got = sscanf(text.c_str(), kEntryFormat, &x.desc_tile_w, &x.cost_dchunk,
+                         &x.blocks_per_cu[0], &x.blocks_per_cu[1], &x.blocks_per_cu[2],
+                         &x.blocks_per_cu[3], &x.cost_mfma, &x.batch_tile_h, &x.pair_desc_th,
+                         &x.pair_right_px, &x.mfma_min_dmax, ms);
+  if (got != 12) return false;
+  bsm_tuning c;
+  tuning_to_c(x, &c);
+  if (check_tuning(&c) != BSM_OK) return false;
+  *t = x;
+  return true;
+}
+
+bool cache_write(const char *path, const std::vector<std::pair<std::string, std::string>> &e) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return false;
+    f << "{\n";
+    for (size_t i = 0; i < e.size(); ++i)
+      f << "\"" << e[i].first << "\": " << e[i].second << (i + 1 < e.size() ? ",\n" : "\n");
+    f << "}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+}  // namespace bsm
+
 extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t npairs,
                                    int32_t reps, void *hip_stream, bsm_tuning *best,
                                    double *best_ms) {
@@ -353,72 +601,69 @@ extern "C" bsm_status bsm_autotune(bsm_ctx *ctx, const bsm_pair *pairs, int32_t 
   OnDevice g(ctx->device);
   if (g.err != hipSuccess) return device_fail(ctx, g.err, "hipSetDevice");
   if ((st = ensure_batch_state(ctx)) != BSM_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  hipError_t e;
-  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
-    if (t0) (void)hipEventDestroy(t0);
-    return device_fail(ctx, e, "autotune events");
-  }
-  Tuning best_t = ctx->dt.tune;
+  Tuning best_t;
   double best_time = -1;
-  // Candidates: describe tile width x height x share of the describe
-  // workgroups that start on the descriptor-only tiles (one in 3 .. 8) x,
-  // only when a pair has a volume (they are the bitwise kernel's), cost
-  // window and cost persistent occupancy.  Each runs on a copy of the
-  // tables; the batch state recaptures its graph whenever the launch
-  // choices change.
-  bool any_volume = false;
-  for (int i = 0; i < npairs; ++i) any_volume = any_volume || pairs[i].cost != nullptr;
-  std::vector<Tuning> candidates;
-  for (int tw : {16, 32})
-    for (int th : {8, 16})
-      for (int dc : {32, 64})
-        for (int cost_bpc : {0, 2})
-          for (int right_every : {3, 4, 5, 6, 8}) {
-            if (!any_volume && (dc == 32 || cost_bpc == 2)) continue;
-            Tuning t;
-            t.desc_tile_w = tw;
-            t.batch_tile_h = th;
-            t.cost_dchunk = dc;
-            t.blocks_per_cu[2] = right_every;
-            t.blocks_per_cu[3] = cost_bpc;
-            candidates.push_back(t);
-          }
-  for (const Tuning &cand : candidates) {
-    DeviceTables dt = ctx->dt;
-    dt.tune = cand;
-    // one untimed run (captures the graph), then the timed runs
-    if ((st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s)) != BSM_OK) break;
-    if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
-    for (int r = 0; r < reps && st == BSM_OK; ++r)
-      st = batch_run(ctx, *ctx->batch, dt, pairs, npairs, s);
-    if (st != BSM_OK) break;
-    if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
-      break;
-    float ms = 0;
-    if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
-    const double per = ms / reps;
-    if (best_time < 0 || per < best_time) {
-      best_time = per;
-      best_t = cand;
+  st = autotune_search(ctx, pairs, npairs, reps, static_cast<hipStream_t>(hip_stream), &best_t,
+                       &best_time);
+  if (st != BSM_OK) return st;
+  set_context_tuning(ctx, best_t);
+  if (best) tuning_to_c(best_t, best);
+  if (best_ms) *best_ms = best_time;
+  return BSM_OK;
+}
+
+extern "C" bsm_status bsm_autotune_cached(bsm_ctx *ctx, const bsm_pair *pairs, int32_t npairs,
+                                          int32_t reps, void *hip_stream, const char *cache_path,
+                                          bsm_tuning *best, double *best_ms, int32_t *hit) {
+  clear_error();
+  bsm_status st;
+  if ((st = check_alive(ctx)) != BSM_OK) return st;
+  if ((st = validate_pairs(pairs, npairs)) != BSM_OK) return st;
+  if (npairs < 1 || reps < 1 || reps > 1000)
+    return fail(BSM_EINVAL, "need npairs >= 1 and 1 <= reps <= 1000");
+  if (hit) *hit = 0;
+  const std::string key = cache_path ? autotune_key(ctx, pairs, npairs) : std::string();
+  std::vector<std::pair<std::string, std::string>> entries;
+  if (cache_path) {
+    entries = cache_read(cache_path);
+    for (const auto &en : entries) {
+      Tuning t;
+      double ms = 0;
+      if (en.first == key && parse_entry(en.second, &t, &ms)) {
+        set_context_tuning(ctx, t);
+        if (best) tuning_to_c(t, best);
+        if (best_ms) *best_ms = ms;
+        if (hit) *hit = 1;
+        return BSM_OK;
+      }
     }
   }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-  if (st == BSM_OK && e != hipSuccess) st = device_fail(ctx, e, "autotune timing");
-  if (st == BSM_OK) {
-    std::lock_guard<std::mutex> lk(ctx->tune_mu);
-    ctx->dt.tune = best_t;
-  }
+  OnDevice g(ctx->device);
+  if (g.err != hipSuccess) return device_fail(ctx, g.err, "hipSetDevice");
+  if ((st = ensure_batch_state(ctx)) != BSM_OK) return st;
+  Tuning best_t;
+  double best_time = -1;
+  st = autotune_search(ctx, pairs, npairs, reps, static_cast<hipStream_t>(hip_stream), &best_t,
+                       &best_time);
   if (st != BSM_OK) return st;
-  if (best) {
-    best->desc_tile_w = best_t.desc_tile_w;
-    best->cost_dchunk = best_t.cost_dchunk;
-    for (int i = 0; i < 4; ++i) best->blocks_per_cu[i] = best_t.blocks_per_cu[i];
-    best->cost_mfma = best_t.cost_mfma;
-    best->batch_tile_h = best_t.batch_tile_h;
-  }
+  set_context_tuning(ctx, best_t);
+  if (best) tuning_to_c(best_t, best);
   if (best_ms) *best_ms = best_time;
+  if (cache_path) {
+    char text[512];
+    snprintf(text, sizeof text, kEntryFormat, best_t.desc_tile_w, best_t.cost_dchunk,
+             best_t.blocks_per_cu[0], best_t.blocks_per_cu[1], best_t.blocks_per_cu[2],
+             best_t.blocks_per_cu[3], best_t.cost_mfma, best_t.batch_tile_h, best_t.pair_desc_th,
+             best_t.pair_right_px, best_t.mfma_min_dmax, best_time);
+    bool replaced = false;
+    for (auto &en : entries)
+      if (en.first == key) {
+        en.second = text;
+        replaced = true;
+      }
+    if (!replaced) entries.emplace_back(key, text);
+    if (!cache_write(cache_path, entries))
+      return fail(BSM_EINVAL, "tuned, but could not write the cache file %s", cache_path);
+  }
   return BSM_OK;
 }

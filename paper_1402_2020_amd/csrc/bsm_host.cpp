@@ -369,6 +369,31 @@ DeviceTables mirrored_tables(const bsm_ctx *ctx) {
 
 }  // namespace bsm
 
+namespace bsm {
+
+bsm_status check_tuning(const bsm_tuning *in) {
+  if (!in) return fail(BSM_EINVAL, "tuning must not be NULL");
+  if (in->desc_tile_w != 16 && in->desc_tile_w != 32)
+    return fail(BSM_EINVAL, "desc_tile_w must be 16 or 32");
+  if (in->cost_dchunk != 32 && in->cost_dchunk != 64)
+    return fail(BSM_EINVAL, "cost_dchunk must be 32 or 64");
+  for (int i = 0; i < 4; ++i)
+    if (in->blocks_per_cu[i] < 0 || in->blocks_per_cu[i] > 64)
+      return fail(BSM_EINVAL, "blocks_per_cu[%d] out of [0, 64]", i);
+  if (in->cost_mfma != 0 && in->cost_mfma != 1) return fail(BSM_EINVAL, "cost_mfma must be 0 or 1");
+  if (in->batch_tile_h != 8 && in->batch_tile_h != 16)
+    return fail(BSM_EINVAL, "batch_tile_h must be 8 or 16");
+  if (in->pair_desc_th != 0 && in->pair_desc_th != 4 && in->pair_desc_th != 8)
+    return fail(BSM_EINVAL, "pair_desc_th must be 0, 4 or 8");
+  if (in->pair_right_px != 0 && in->pair_right_px != 1 && in->pair_right_px != 4)
+    return fail(BSM_EINVAL, "pair_right_px must be 0, 1 or 4");
+  if (in->mfma_min_dmax < 2 || in->mfma_min_dmax > 257)
+    return fail(BSM_EINVAL, "mfma_min_dmax must be in [2, 257]");
+  return BSM_OK;
+}
+
+}  // namespace bsm
+
 using namespace bsm;
 
 // ===========================================================================
@@ -615,6 +640,9 @@ bsm_status bsm_get_tuning(const bsm_ctx *ctx, bsm_tuning *out) {
   for (int i = 0; i < 4; ++i) out->blocks_per_cu[i] = t.blocks_per_cu[i];
   out->cost_mfma = t.cost_mfma;
   out->batch_tile_h = t.batch_tile_h;
+  out->pair_desc_th = t.pair_desc_th;
+  out->pair_right_px = t.pair_right_px;
+  out->mfma_min_dmax = t.mfma_min_dmax;
   return BSM_OK;
 }
 
@@ -622,23 +650,16 @@ bsm_status bsm_set_tuning(bsm_ctx *ctx, const bsm_tuning *in) {
   clear_error();
   bsm_status st;
   if ((st = check_alive(ctx)) != BSM_OK) return st;
-  if (!in) return fail(BSM_EINVAL, "tuning must not be NULL");
-  if (in->desc_tile_w != 16 && in->desc_tile_w != 32)
-    return fail(BSM_EINVAL, "desc_tile_w must be 16 or 32");
-  if (in->cost_dchunk != 32 && in->cost_dchunk != 64)
-    return fail(BSM_EINVAL, "cost_dchunk must be 32 or 64");
-  for (int i = 0; i < 4; ++i)
-    if (in->blocks_per_cu[i] < 0 || in->blocks_per_cu[i] > 64)
-      return fail(BSM_EINVAL, "blocks_per_cu[%d] out of [0, 64]", i);
-  if (in->cost_mfma != 0 && in->cost_mfma != 1) return fail(BSM_EINVAL, "cost_mfma must be 0 or 1");
-  if (in->batch_tile_h != 8 && in->batch_tile_h != 16)
-    return fail(BSM_EINVAL, "batch_tile_h must be 8 or 16");
+  if ((st = check_tuning(in)) != BSM_OK) return st;
   Tuning t;
   t.desc_tile_w = in->desc_tile_w;
   t.cost_dchunk = in->cost_dchunk;
   for (int i = 0; i < 4; ++i) t.blocks_per_cu[i] = in->blocks_per_cu[i];
   t.cost_mfma = in->cost_mfma;
   t.batch_tile_h = in->batch_tile_h;
+  t.pair_desc_th = in->pair_desc_th;
+  t.pair_right_px = in->pair_right_px;
+  t.mfma_min_dmax = in->mfma_min_dmax;
   {
     // batch states compare this with the choices their graphs hold
     std::lock_guard<std::mutex> lk(ctx->tune_mu);

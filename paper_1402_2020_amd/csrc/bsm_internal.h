@@ -48,6 +48,10 @@ struct Tuning {
   int blocks_per_cu[4] = {0, 0, 0, 0};  // persistent batch grids (0: all that fit)
   int cost_mfma = 1;                    // no-volume cost + WTA on the matrix cores
   int batch_tile_h = 16;                // describe+mask tile height of the batch: 8 or 16
+  // Single-pair launch choices (0 = the size rule of the launcher).
+  int pair_desc_th = 0;                 // describe+mask tile height: 4 or 8 rows
+  int pair_right_px = 0;                // descriptor-only pixels per lane: 1 or 4
+  int mfma_min_dmax = 17;               // smallest dmax on the matrix-core cost kernel
 };
 
 // Device-side view of the constant data of a context.
@@ -106,7 +110,12 @@ struct BatchWork {
 struct BatchLaunch {
   const BatchWork *work;  // device pointer
   int *counters;          // device pointer (== work->counters)
+  // Optional (eager launches only): kBatchMarks events recorded on the
+  // stream before the colour stage and after each of the four stages.
+  const hipEvent_t *marks = nullptr;
 };
+constexpr int kBatchStages = 4;  // colour, describe (both views), cost, cost with a volume
+constexpr int kBatchMarks = kBatchStages + 1;
 
 // ---- kernel launchers (bsm_kernels.hip) -----------------------------------
 hipError_t launch_color(const uint8_t *img, int W, int H, int stride,
@@ -144,6 +153,11 @@ bsm_status batch_state_create(bsm_ctx *ctx, BatchState **out);
 // launch choices on stream s.
 bsm_status batch_run(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt, const bsm_pair *pairs,
                      int npairs, hipStream_t s);
+// The persistent path with its stages launched directly on s (no graph) and
+// `marks` (kBatchMarks events) recorded between them.
+bsm_status batch_run_marked(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
+                            const bsm_pair *pairs, int npairs, hipStream_t s,
+                            const hipEvent_t *marks);
 
 // ---- device scratch with stream-ordered reuse ---------------------------
 // A growable device buffer.  Every use is recorded with an event; a use on
@@ -238,6 +252,8 @@ bsm_status validate_dmax(int W, int dmax);
 bool aligned8(const void *p);
 bool aligned16(const void *p);
 size_t match_scratch_bytes(const bsm_ctx *ctx, int W, int H);
+// BSM_EINVAL (with a message) unless every field is in its documented range.
+bsm_status check_tuning(const bsm_tuning *t);
 // The context's tables with the mirrored pattern in place of the pattern.
 DeviceTables mirrored_tables(const bsm_ctx *ctx);
 // `side`: a lane for the other view's work (nullptr: everything on s).

@@ -1380,14 +1380,18 @@ __global__ __launch_bounds__(64) void k_cost_wta_chunked(const uint64_t *__restr
 
 // ===========================================================================
 // Voting refinement (Eq. 9-10) of the pixels the left/right check marked
-// invalid.  One wave per pixel: the lanes walk the (2 radius + 1)^2 window,
-// every valid pixel p adds its bilateral weight
-// exp(-(c / lambda_c + e / lambda_e)) (c: Euclidean distance of the Lab8
-// colours, e: of the positions) to the wave's histogram over d in LDS, then
-// the wave takes the largest vote, the lowest d among equal votes.  A pixel
-// without voters keeps its fallback disparity; valid pixels keep theirs.
-// Votes are summed in fp32 (the order of the LDS additions is the
-// hardware's).
+// invalid.  One wave per pixel: the lanes walk the (2 radius + 1)^2 window
+// 64 positions at a time, and every valid pixel p brings its bilateral
+// weight exp(-(c / lambda_c + e / lambda_e)) (c: Euclidean distance of the
+// Lab8 colours, e: of the positions) as a vote for its disparity.  Within
+// one step the votes for one d are summed by a fixed butterfly over the
+// lanes (zeros from lanes voting for another d), taking the step's d values
+// in the order of their lowest lane, and one lane adds the sum to the
+// wave's histogram bin in LDS.  Every bin thus receives its votes in the
+// same order on every run, so the fp32 sums, and the argmax, are
+// deterministic.  The wave then takes the largest vote, the lowest d among
+// equal votes.  A pixel without voters keeps its fallback disparity; valid
+// pixels keep theirs.
 // ===========================================================================
 constexpr int kVoteWaves = 4;
 
@@ -1409,22 +1413,41 @@ __global__ __launch_bounds__(64 * kVoteWaves) void k_vote_refine(
   bool voted = false;
   if (refine) {
     const uint32_t cx = packed[x];
-    const int side = 2 * radius + 1;
-    for (int i = lane; i < side * side; i += 64) {
-      const int dy = i / side - radius, dx = i % side - radius;
-      const int pu = u + dx, pv = v + dy;
-      if (pu < 0 || pu >= W || pv < 0 || pv >= H) continue;
-      const size_t p = (size_t)pv * W + pu;
-      const int d = checked[p];
-      if (d < 0 || d >= dmax) continue;
-      const uint32_t cp = packed[p];
-      const float dl = (float)(int)(cx & 0xff) - (float)(int)(cp & 0xff);
-      const float da = (float)(int)((cx >> 8) & 0xff) - (float)(int)((cp >> 8) & 0xff);
-      const float db = (float)(int)((cx >> 16) & 0xff) - (float)(int)((cp >> 16) & 0xff);
-      const float c = sqrtf(dl * dl + da * da + db * db);
-      const float e = sqrtf((float)(dx * dx + dy * dy));
-      atomicAdd(&hist[d], expf(-(c / lambda_c + e / lambda_e)));
-      voted = true;
+    const int side = 2 * radius + 1, area = side * side;
+    for (int base = 0; base < area; base += 64) {
+      const int i = base + lane;
+      int d = -1;
+      float wgt = 0.0f;
+      if (i < area) {
+        const int dy = i / side - radius, dx = i % side - radius;
+        const int pu = u + dx, pv = v + dy;
+        if (pu >= 0 && pu < W && pv >= 0 && pv < H) {
+          const size_t p = (size_t)pv * W + pu;
+          const int dp = checked[p];
+          if (dp >= 0 && dp < dmax) {
+            const uint32_t cp = packed[p];
+            const float dl = (float)(int)(cx & 0xff) - (float)(int)(cp & 0xff);
+            const float da = (float)(int)((cx >> 8) & 0xff) - (float)(int)((cp >> 8) & 0xff);
+            const float db = (float)(int)((cx >> 16) & 0xff) - (float)(int)((cp >> 16) & 0xff);
+            const float c = sqrtf(dl * dl + da * da + db * db);
+            const float e = sqrtf((float)(dx * dx + dy * dy));
+            d = dp;
+            wgt = expf(-(c / lambda_c + e / lambda_e));
+          }
+        }
+      }
+      unsigned long long pending = __ballot(d >= 0);
+      if (pending) voted = true;
+      while (pending) {  // uniform
+        const int leader = __builtin_ctzll(pending);
+        const int dl = __shfl(d, leader);
+        const bool mine = d == dl;
+        float sum = mine ? wgt : 0.0f;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off);
+        if (lane == 0) hist[dl] += sum;  // the bin's only writer
+        pending &= ~__ballot(mine);
+      }
     }
   }
   __syncthreads();
@@ -1450,8 +1473,7 @@ __global__ __launch_bounds__(64 * kVoteWaves) void k_vote_refine(
       best_d = od;
     }
   }
-  const bool any = __ballot(voted) != 0;
-  if (lane == 0) out[x] = any ? best_d : fallback[x];
+  if (lane == 0) out[x] = voted ? best_d : fallback[x];
 }
 
 // ===========================================================================
@@ -1733,7 +1755,9 @@ hipError_t launch_describe_mask_t(const uint32_t *packed, int W, int H, const De
   DescribeConsts c = describe_consts(t);
   c.pitch = t.left_pitch_for(TW);
   const long long tall_tiles = (long long)((W + TW - 1) / TW) * ((H + kDescTH - 1) / kDescTH);
-  if (tall_tiles >= kDescTallMinTiles) {
+  const bool tall = t.tune.pair_desc_th ? t.tune.pair_desc_th == kDescTH
+                                        : tall_tiles >= kDescTallMinTiles;
+  if (tall) {
     dim3 grid((W + TW - 1) / TW, (H + kDescTH - 1) / kDescTH);
     hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTH>), grid, dim3(kDescThreads),
                        mask_lds_bytes(t, TW, kDescTH), s, packed, W, H, c, desc, mask);
@@ -1839,10 +1863,18 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
                           hipStream_t s) {
   const Tuning &tu = t.tune;
   const BatchWork *bw = bl.work;
+  // Optional stage marks (eager launches): before the colour stage and
+  // after each stage.
+  auto mark = [&](int i) -> hipError_t {
+    return bl.marks ? hipEventRecord(bl.marks[i], s) : hipSuccess;
+  };
+  hipError_t me;
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bl.counters);
+  if ((me = mark(0)) != hipSuccess) return me;
   const int g0 = persistent_grid(k_batch_color, kColorThreads, 0, tu.blocks_per_cu[0]);
   hipLaunchKernelGGL(k_batch_color, dim3(g0), dim3(kColorThreads), 0, s, bw, t.lin, t.f,
                      t.mq, use_mask);
+  if ((me = mark(1)) != hipSuccess) return me;
   {
     // both describe stages (the describe+mask queue is empty without a mask)
     static const hipError_t attr =
@@ -1858,6 +1890,7 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
     hipLaunchKernelGGL((k_batch_describe<NW, TW, TH>), dim3(g1), dim3(kDescThreads), lds, s, bw,
                        cm, right_consts(t), use_mask ? right_every : 1);
   }
+  if ((me = mark(2)) != hipSuccess) return me;
   {
     // pairs without a volume, then pairs with one (each kernel's queues are
     // empty when the batch has no pair of its kind)
@@ -1876,12 +1909,15 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
     if (use_mask) {
       if (tu.cost_mfma) BSM_LAUNCH_BATCH_COST_MFMA(true);
       else BSM_LAUNCH_BATCH_COST(true, false);
+      if ((me = mark(3)) != hipSuccess) return me;
       BSM_LAUNCH_BATCH_COST(true, true);
     } else {
       if (tu.cost_mfma) BSM_LAUNCH_BATCH_COST_MFMA(false);
       else BSM_LAUNCH_BATCH_COST(false, false);
+      if ((me = mark(3)) != hipSuccess) return me;
       BSM_LAUNCH_BATCH_COST(false, true);
     }
+    if ((me = mark(4)) != hipSuccess) return me;
 #undef BSM_LAUNCH_BATCH_COST
 #undef BSM_LAUNCH_BATCH_COST_MFMA
   }
@@ -1991,7 +2027,9 @@ hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTab
     if (attr4 != hipSuccess) return attr4;
     const int rows = (H + kRightTH - 1) / kRightTH;
     const int wide = (W + kRightTW - 1) / kRightTW;
-    if ((long long)wide * rows >= kRightWideMinBlocks) {
+    const bool four = t.tune.pair_right_px ? t.tune.pair_right_px == kRightPx
+                                           : (long long)wide * rows >= kRightWideMinBlocks;
+    if (four) {
       hipLaunchKernelGGL(k_describe_right<kRightPx>, dim3(wide, rows), dim3(kRightThreads),
                          right_lds_bytes(kRightPx, t.radius, t.right_pitch), s, packed, W, H,
                          right_consts(t), desc);
@@ -2017,7 +2055,7 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const u
   const int dc = t.tune.cost_dchunk;
   // Matrix-core kernel, except for short disparity ranges (a tile computes
   // at least two 32-wide blocks, most of them wasted when dmax <= 16).
-  if (t.tune.cost_mfma && dmax > 16 && (!cost || dmax <= kMfmaVolMaxD)) {
+  if (t.tune.cost_mfma && dmax >= t.tune.mfma_min_dmax && (!cost || dmax <= kMfmaVolMaxD)) {
     switch (nw) {
       case 1: return launch_cost_mfma<1>(descL, maskL, descR, W, H, dmax, disp, cost, s);
       case 2: return launch_cost_mfma<2>(descL, maskL, descR, W, H, dmax, disp, cost, s);

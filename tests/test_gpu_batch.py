@@ -233,7 +233,8 @@ def test_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
     ctx, pat = _ctx(bsm, orc, 1024, 31, seed=11)
     sc, (wd, wc) = _tuning_scene(orc, pat)
     ctx.set_tuning(tuning)
-    assert ctx.tuning() == tuning
+    got = ctx.tuning()
+    assert {k: got[k] for k in tuning} == tuning
     L, R = _dev(torch, sc.left), _dev(torch, sc.right)
     disp, cost = ctx.match(L, R, sc.dmax, want_cost=True)
     disp_nv, _ = ctx.match(L, R, sc.dmax, want_cost=False)
@@ -256,7 +257,11 @@ def test_set_tuning_validates(torch_cuda, bsm, orc):
     for bad in (dict(desc_tile_w=8, cost_dchunk=64), dict(desc_tile_w=16, cost_dchunk=48),
                 dict(desc_tile_w=16, cost_dchunk=64, blocks_per_cu=[0, 0, 0, 65]),
                 dict(desc_tile_w=16, cost_dchunk=64, cost_mfma=2),
-                dict(desc_tile_w=16, cost_dchunk=64, batch_tile_h=12)):
+                dict(desc_tile_w=16, cost_dchunk=64, batch_tile_h=12),
+                dict(desc_tile_w=16, cost_dchunk=64, pair_desc_th=6),
+                dict(desc_tile_w=16, cost_dchunk=64, pair_right_px=2),
+                dict(desc_tile_w=16, cost_dchunk=64, mfma_min_dmax=1),
+                dict(desc_tile_w=16, cost_dchunk=64, mfma_min_dmax=258)):
         assert bsm.bsm_set_tuning(ctx.h, bsm.Tuning.from_dict(bad)) == bsm.EINVAL
     ctx.close()
 
@@ -268,8 +273,88 @@ def test_autotune_picks_a_candidate_and_keeps_results(torch_cuda, bsm, orc):
     scenes = _scenes(5, 0.15)
     items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
     best, ms = ctx.autotune(items, reps=2)
-    assert best in TUNINGS or best["desc_tile_w"] in (16, 32)
+    assert best["desc_tile_w"] in (16, 32) and best["batch_tile_h"] in (8, 16)
     assert ms > 0
+    assert ctx.tuning() == best
+    _check_batch_vs_oracle(torch, ctx, pat, orc, scenes, False)
+    ctx.close()
+
+
+PAIR_TUNINGS = [dict(desc_tile_w=tw, cost_dchunk=64, pair_desc_th=th, pair_right_px=px,
+                     mfma_min_dmax=md)
+                for tw in (16, 32) for th in (4, 8) for px in (1, 4) for md in (2, 17, 257)
+                if (tw, th, px) in ((16, 4, 1), (32, 8, 4)) or md == 17]
+
+
+@pytest.mark.parametrize("tuning", PAIR_TUNINGS,
+                         ids=lambda t: f"tw{t['desc_tile_w']}-th{t['pair_desc_th']}-"
+                         f"px{t['pair_right_px']}-md{t['mfma_min_dmax']}")
+def test_single_pair_tunings_do_not_change_results(torch_cuda, bsm, orc, tuning):
+    # describe tile height, descriptor-only pixels per lane and the dmax
+    # from which the matrix-core cost kernel runs (2: even dmax 5 on the
+    # matrix cores; 257: the bitwise kernel everywhere), on a pair whose
+    # width is not a multiple of any tile and on a short disparity range
+    torch = torch_cuda
+    _say(f"case: single-pair tuning {tuning}")
+    ctx, pat = _ctx(bsm, orc, 1024, 31, seed=11)
+    sc, (wd, wc) = _tuning_scene(orc, pat)
+    ctx.set_tuning(tuning)
+    L, R = _dev(torch, sc.left), _dev(torch, sc.right)
+    disp, cost = ctx.match(L, R, sc.dmax, want_cost=True)
+    disp_nv, _ = ctx.match(L, R, sc.dmax)
+    small = synth.slanted_scene(34, 77, 23, 5)
+    ws, wsc = orc.match(small.left, small.right, pat, 5, want_cost=True)
+    ds, cs = ctx.match(_dev(torch, small.left), _dev(torch, small.right), 5, want_cost=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(disp.cpu().numpy(), wd)
+    assert np.array_equal(cost.cpu().numpy(), wc)
+    assert np.array_equal(disp_nv.cpu().numpy(), wd)
+    assert np.array_equal(ds.cpu().numpy(), ws)
+    assert np.array_equal(cs.cpu().numpy(), wsc)
+    ctx.close()
+
+
+def test_batch_stage_times_keep_results(torch_cuda, bsm, orc):
+    # the eagerly launched, event-timed batch writes what the graph writes
+    torch = torch_cuda
+    _say("case: bsm_batch_stage_times on 6 small uneven pairs")
+    ctx, pat = _ctx(bsm, orc, 256, 15)
+    scenes = _scenes(6, 0.2)
+    items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
+    want = [d.clone() for d, _ in ctx.match_batch(items)]
+    pairs, outs, keep = ctx._pairs(items, False)
+    st, ms = bsm.bsm_batch_stage_times(ctx.h, pairs, None)
+    assert st == bsm.OK, bsm.bsm_last_error()
+    assert ms[0] > 0 and ms[1] > 0 and ms[2] > 0 and ms[3] >= 0
+    torch.cuda.synchronize()
+    for w, (d, _) in zip(want, outs):
+        assert torch.equal(w, d)
+    # four pairs take the per-pair path, which has no stages
+    st, _ = bsm.bsm_batch_stage_times(ctx.h, pairs[:4], None)
+    assert st == bsm.EINVAL
+    del keep
+    ctx.close()
+
+
+def test_autotune_cache_miss_then_hit(torch_cuda, bsm, orc, tmp_path):
+    import json
+    torch = torch_cuda
+    _say("case: bsm_autotune_cached, miss then hit, batch and single pair")
+    ctx, pat = _ctx(bsm, orc, 256, 15)
+    path = str(tmp_path / "tuning.json")
+    scenes = _scenes(5, 0.15)
+    items = [(_dev(torch, s.left), _dev(torch, s.right), s.dmax) for s in scenes]
+    best, ms, hit = ctx.autotune_cached(items, path, reps=1)
+    assert not hit and ms > 0
+    one, ms1, hit1 = ctx.autotune_cached(items[:1], path, reps=1)
+    assert not hit1 and one["pair_desc_th"] in (4, 8) and one["pair_right_px"] in (1, 4)
+    data = json.load(open(path))
+    assert len(data) == 2
+    keys = sorted(data)
+    assert any(" batch " in k for k in keys) and any(" pairs " in k for k in keys)
+    ctx.set_tuning(dict(desc_tile_w=16, cost_dchunk=64))
+    again, ms2, hit2 = ctx.autotune_cached(items, path, reps=1)
+    assert hit2 and again == best and ms2 == pytest.approx(ms, rel=1e-6)
     assert ctx.tuning() == best
     _check_batch_vs_oracle(torch, ctx, pat, orc, scenes, False)
     ctx.close()

@@ -4,7 +4,8 @@ fp64 in the oracle, so the argmax is compared as follows: valid pixels and
 pixels without voters must match exactly; a refined pixel must take the
 oracle's disparity, or one whose oracle vote is within 1e-4 (relative) of
 the oracle's largest vote (an fp32 sum of at most 127^2 terms in (0, 1]
-carries a relative error far below that)."""
+carries a relative error far below that).  Votes are summed in a fixed
+order, so repeated runs agree bit for bit."""
 import sys
 
 import numpy as np
@@ -108,4 +109,24 @@ def test_vote_refine_validation(torch_cuda, bsm, orc):
     with pytest.raises(bsm.BsmError) as e:
         ctx.vote_refine(img, d, d.clone(), 4, out=d)        # out aliases checked
     assert e.value.status == bsm.EINVAL
+    ctx.close()
+
+
+def test_vote_refine_is_deterministic(torch_cuda, bsm, orc):
+    # The votes are summed in a fixed order, so repeated runs on the same
+    # input give bit-equal maps (floating-point atomics would not).
+    torch = torch_cuda
+    p = synth.CONFIG_PARAMS[1]
+    _say("case: vote_refine determinism, config scene 1, radius 15, 4 runs")
+    sc = synth.config_scene(1)
+    pat = orc.make_pattern(synth.PATTERN_SEED, p["n"], p["S"], p["sigma"])
+    ctx = bsm.Context(p["n"], p["S"], p["sigma"], pattern=pat)
+    L, R = _dev(torch, sc.left), _dev(torch, sc.right)
+    dl, _ = ctx.match(L, R, p["dmax"])
+    dr, _ = ctx.match_right(L, R, p["dmax"])
+    chk = ctx.lr_check(dl, dr, tol=1)
+    first = ctx.vote_refine(L, chk, dl, p["dmax"], radius=15).cpu().numpy()
+    for _ in range(3):
+        again = ctx.vote_refine(L, chk, dl, p["dmax"], radius=15).cpu().numpy()
+        assert np.array_equal(first, again)
     ctx.close()
