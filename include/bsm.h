@@ -187,6 +187,25 @@ bsm_status bsm_match(bsm_ctx *ctx, const uint8_t *left, const uint8_t *right,
                      int32_t W, int32_t H, int32_t stride, int32_t dmax,
                      int32_t *disp, int16_t *cost, void *hip_stream);
 
+/* bsm_match for callers that cannot allocate device memory (work under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as bsm_match; the pair's scratch (two
+ * colour planes and three descriptor planes, bsm_footprint without the
+ * volume) lives in a fixed device array of the library, of
+ * BSM_NOALLOC_MAX_BYTES (64 MiB) per GPU, held from bsm_create until the
+ * process ends.  The call allocates nothing and creates no stream or event:
+ * all its work is enqueued on hip_stream.  A 450 x 375 pair at n = 1024
+ * fits; a pair whose scratch exceeds the array returns BSM_ETOOBIG before
+ * any device work.  Every context on one GPU shares that GPU's array and
+ * nothing in it needs clearing (each call overwrites what it reads), but
+ * calls whose work overlaps on one GPU race: the caller must order them
+ * (one stream, or events between streams). */
+#define BSM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+bsm_status bsm_match_noalloc(bsm_ctx *ctx, const uint8_t *left,
+                             const uint8_t *right, int32_t W, int32_t H,
+                             int32_t stride, int32_t dmax, int32_t *disp,
+                             int16_t *cost, void *hip_stream);
+
 /* Right-reference matching: the second depth map of the left/right check
  * that opens the refinement step of Section 3.  The right view is the
  * reference: pixel (u, v) of the right view is compared with (u + d, v) of

@@ -19,6 +19,7 @@ INVALID_COST = 32767
 # Every symbol include/bsm.h declares.
 EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "bsm_pattern",
            "bsm_footprint", "bsm_color", "bsm_describe", "bsm_describe_packed", "bsm_cost_wta", "bsm_match",
+           "bsm_match_noalloc",
            "bsm_match_right", "bsm_lr_check", "bsm_vote_refine",
            "bsm_match_batch", "bsm_batch_stage_times", "bsm_get_tuning", "bsm_set_tuning",
            "bsm_autotune", "bsm_autotune_cached",
@@ -110,6 +111,7 @@ def load():
         "bsm_describe_packed": ([vp, vp, i32, i32, vp, vp, vp], st),
         "bsm_cost_wta": ([vp, vp, vp, vp, i32, i32, i32, vp, vp, vp], st),
         "bsm_match": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
+        "bsm_match_noalloc": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
         "bsm_match_right": ([vp, vp, vp, i32, i32, i32, i32, vp, vp, vp], st),
         "bsm_lr_check": ([vp, vp, vp, i32, i32, i32, vp, vp], st),
         "bsm_vote_refine": ([vp, vp, i32, i32, i32, vp, vp, i32, i32, C.c_float, C.c_float, vp, vp],
@@ -201,6 +203,10 @@ def bsm_cost_wta(ctx, descL, maskL, descR, W, H, dmax, disp, cost, stream):
 
 def bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
     return load().bsm_match(ctx, left, right, W, H, stride, dmax, disp, cost, stream)
+
+
+def bsm_match_noalloc(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
+    return load().bsm_match_noalloc(ctx, left, right, W, H, stride, dmax, disp, cost, stream)
 
 
 def bsm_match_right(ctx, left, right, W, H, stride, dmax, disp, cost, stream):
@@ -385,6 +391,24 @@ class Context:
             cost = torch.empty((dmax, H, W), dtype=torch.int16, device=left.device)
         _check(bsm_match(self.h, _ptr(left), _ptr(right), W, H, st, dmax, _ptr(disp),
                          _ptr(cost), _stream(stream)), "bsm_match")
+        return disp, cost
+
+    def match_noalloc(self, left, right, dmax, want_cost=False, disp=None, cost=None,
+                      stream=None):
+        """bsm_match with its scratch in the library's fixed device array
+        (no allocation inside the call; outputs are allocated here unless
+        given)."""
+        import torch
+        left, W, H, st = self._img(left)
+        right, W2, H2, _ = self._img(right)
+        if (W2, H2) != (W, H):
+            raise ValueError("left and right must have the same shape")
+        if disp is None:
+            disp = torch.empty((H, W), dtype=torch.int32, device=left.device)
+        if cost is None and want_cost:
+            cost = torch.empty((dmax, H, W), dtype=torch.int16, device=left.device)
+        _check(bsm_match_noalloc(self.h, _ptr(left), _ptr(right), W, H, st, dmax, _ptr(disp),
+                                 _ptr(cost), _stream(stream)), "bsm_match_noalloc")
         return disp, cost
 
     def match_right(self, left, right, dmax, want_cost=False, disp=None, cost=None, stream=None):

@@ -71,24 +71,6 @@ double now_seconds() {
   return ts.tv_sec + 1e-9 * ts.tv_nsec;
 }
 
-// RAII: makes the context's device current and restores the caller's.
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-    if (prev_ != dev) err_ = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
-  }
-  hipError_t err() const { return err_; }
-
- private:
-  int prev_ = -1;
-  hipError_t err_ = hipSuccess;
-};
-
 // ---------------------------------------------------------------------------
 // Point-pair pattern (Section 3, after Eq. 2).  Coordinates are drawn from
 // splitmix64 (Steele, Lea and Flood, 2014) through the basic Box-Muller
@@ -485,6 +467,11 @@ bsm_status bsm_create(const bsm_params *p, int32_t hip_device, bsm_ctx **out) {
   DeviceGuard g(hip_device);
   if (g.err() != hipSuccess) return device_fail(nullptr, g.err(), "hipSetDevice");
   hipError_t e;
+  // the device address of bsm_match_noalloc's fixed array, once per device
+  if ((e = noalloc_setup(hip_device)) != hipSuccess) {
+    bsm_destroy(ctx.release());
+    return device_fail(nullptr, e, "taking the address of the no-allocation scratch array");
+  }
   if ((e = hipMalloc(&ctx->d_pattern, ctx->pattern.size())) != hipSuccess ||
       (e = hipMalloc(&ctx->d_lin, 256 * sizeof(uint16_t))) != hipSuccess ||
       (e = hipMalloc(&ctx->d_f, 65536 * sizeof(uint16_t))) != hipSuccess ||

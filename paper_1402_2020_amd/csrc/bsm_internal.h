@@ -241,6 +241,24 @@ struct bsm_ctx {
 };
 
 namespace bsm {
+// RAII: makes the context's device current and restores the caller's.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) err_ = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
+  }
+  hipError_t err() const { return err_; }
+
+ private:
+  int prev_ = -1;
+  hipError_t err_ = hipSuccess;
+};
+
 // Error plumbing (bsm_host.cpp).
 bsm_status fail(bsm_status st, const char *fmt, ...);
 bsm_status device_fail(bsm_ctx *ctx, hipError_t e, const char *what);
@@ -263,4 +281,8 @@ bsm_status match_on_stream(bsm_ctx *ctx, const uint8_t *left,
                            void *scratch, hipStream_t s, SideLane *side,
                            bool right_reference = false);
 double now_seconds();
+// Entry point without allocation (bsm_noalloc.hip): size of its fixed device
+// array, and its set-up, run once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_setup(int device);
 }  // namespace bsm
