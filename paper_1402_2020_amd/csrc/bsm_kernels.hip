@@ -122,10 +122,9 @@ __global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL
 // image, which is exactly the border rule).  Each wave walks its pixels one
 // at a time with the 64 lanes spread over the point pairs and every pair
 // weight kept in registers.  T, the k-th smallest weight, is the smallest t
-// with #{w <= t} >= k; a probe counts ballot(w <= t) words with scalar
-// popcounts, and the search starts from the wave's previous pixel's T
-// (neighbouring pixels have close thresholds): it gallops away from it in
-// doubling steps until T is bracketed, then bisects.
+// with #{w <= t} >= k: a counting search on the vector unit (see
+// kth_smallest) that starts from the wave's previous pixel's T, since
+// neighbouring pixels have close thresholds.
 //
 // Pair-to-lane maps (NW = nw rounded up to a power of two, padded pairs
 // compare the centre with itself: weight 0, and each shifts the rank of T
@@ -143,7 +142,6 @@ __global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL
 // persistent batch kernel takes the height its tuning names (8 or 16 rows).
 constexpr int kDescTH = 8, kDescTHSmall = 4, kDescThreads = 256;
 constexpr long long kDescTallMinTiles = 4096;  // four rounds of the GPU at four blocks per CU
-constexpr int kGallopStep = 8;  // first step of the threshold search
 
 // Pair index of slot j of lane `lane` (0-based).
 template <int NW>
@@ -174,58 +172,120 @@ __device__ __forceinline__ void for_words(F &&f) {
   }
 }
 
-// #{w <= t} >= k over the wave's weights (t wave-uniform).
-template <int NW>
-__device__ __forceinline__ bool rank_reached(const uint32_t *w, int t, int k) {
-  int count = 0;
-#pragma unroll
-  for (int j = 0; j < NW; ++j) count += __popcll(__ballot(w[j] <= (uint32_t)t));
-  return count >= k;
+// ---- T, the k-th smallest weight (Eq. 6), by a counting search ----------
+// Weights lie in [0, 765] (three byte differences) and sit two per dword in
+// 16-bit halves; a half that holds no weight holds 0x7fff.  The rank of a
+// threshold t, #{w <= t}, is counted on the vector unit: w - (t + 1) is
+// negative exactly when w <= t, v_perm_b32 turns the sign bits of four
+// halves into four bytes of 0x00 / 0xff and v_bcnt_u32_b32 adds 8 per set
+// sign.  A wave reduction with DPP row shifts and row broadcasts sums the
+// lanes' counts.  The search keeps a bracket lo < T <= hi with known ranks
+// (rank(lo) < k <= rank(hi)); the next probe is the secant through the
+// bracket once both ends have been probed, and before that a step of
+// (k - rank) / density from the last probe.  The density (weights per unit
+// of t near T) is a running average over the wave's previous pixels, taken
+// from their first two probes.  The first probe is the previous pixel's T.
+constexpr int kTop = 765;  // largest weight: rank(765) counts every weight
+
+// The state carried from one pixel to the next by a wave.
+struct SearchHint {
+  int t;       // previous pixel's T
+  float dens;  // running average of the rank density near T
+};
+
+// A wave-uniform float in a scalar register.
+__device__ __forceinline__ float uniform_f32(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
 }
 
-// The k-th smallest weight (Eq. 6: T), searched from `guess`.  Weights lie
-// in [0, 765] (three byte differences), so t = 765 always reaches rank k
-// and t = -1 never does.
-template <int NW>
-__device__ __forceinline__ int kth_smallest(const uint32_t *w, int k, int guess) {
-  constexpr int kTop = 765;
-  int lo, hi;  // rank not reached at lo, reached at hi
-  if (rank_reached<NW>(w, guess, k)) {
-    hi = guess;
-    for (int step = kGallopStep;; step <<= 1) {
-      const int t = hi - step;
-      if (t < 0) {
-        lo = -1;
-        break;
-      }
-      if (!rank_reached<NW>(w, t, k)) {
-        lo = t;
-        break;
-      }
+// Packs two weights (each <= 765) into the 16-bit halves of a dword.
+__device__ __forceinline__ uint32_t pack_halves(uint32_t lo, uint32_t hi) {
+  return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+// Halves of a minus halves of b, each mod 2^16 (v_pk_sub_u16).
+__device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+
+// 8 * #{weights of this lane <= t}; t1x2 holds t + 1 in both halves.
+template <int NP>
+__device__ __forceinline__ uint32_t lane_rank8(const uint32_t *P, uint32_t t1x2) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int m = 0; m + 1 < NP; m += 2) {
+    // bytes 0-3: signs of P[m + 1].lo, P[m + 1].hi, P[m].lo, P[m].hi
+    const uint32_t z = __builtin_amdgcn_perm(pk_sub16(P[m], t1x2), pk_sub16(P[m + 1], t1x2),
+                                             0x0b0a0908u);
+    c = __builtin_popcount(z) + c;
+  }
+  if constexpr (NP & 1) {
+    const uint32_t z = __builtin_amdgcn_perm(0u, pk_sub16(P[NP - 1], t1x2), 0x0c0c0908u);
+    c = __builtin_popcount(z) + c;
+  }
+  return c;
+}
+
+// Sum of v over the wave's 64 lanes (wave-uniform result).
+__device__ __forceinline__ int wave_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// #{w <= t} over the wave's packed weights (t wave-uniform, 0 <= t < 765).
+template <int NP>
+__device__ __forceinline__ int wave_rank(const uint32_t *P, int t) {
+  const uint32_t t1 = static_cast<uint32_t>(t + 1);
+  return wave_sum(static_cast<int>(lane_rank8<NP>(P, t1 | (t1 << 16)))) >> 3;
+}
+
+// The k-th smallest of the wave's weights (nwts of them), searched from the
+// hint, which is updated for the next pixel.
+template <int NP>
+__device__ __forceinline__ int kth_smallest(const uint32_t *P, int k, int nwts, SearchHint &h) {
+  int lo = -1, hi = kTop, rlo = 0, rhi = nwts;
+  int t = min(max(h.t, 0), kTop - 1);
+  int t0 = -1, r0 = 0;  // the first probe, for the density estimate
+  for (int probe = 0;; ++probe) {
+    const int r = wave_rank<NP>(P, t);
+    if (probe == 0) {
+      t0 = t;
+      r0 = r;
+    } else if (probe == 1) {
+      // rank density between the first two probes (t != t0)
+      const float d = static_cast<float>(r - r0) * __builtin_amdgcn_rcpf(static_cast<float>(t - t0));
+      h.dens = uniform_f32(0.75f * h.dens + 0.25f * fmaxf(d, 0.25f));
+    }
+    if (r >= k) {
       hi = t;
-    }
-  } else {
-    lo = guess;
-    for (int step = kGallopStep;; step <<= 1) {
-      const int t = lo + step;
-      if (t >= kTop) {
-        hi = kTop;
-        break;
-      }
-      if (rank_reached<NW>(w, t, k)) {
-        hi = t;
-        break;
-      }
+      rhi = r;
+    } else {
       lo = t;
+      rlo = r;
     }
+    if (hi - lo <= 1) break;
+    int next;
+    if (lo >= 0 && hi < kTop) {
+      // secant through the bracket: where the line from (lo, rlo) to
+      // (hi, rhi) reaches k
+      const float f = static_cast<float>((k - rlo) * (hi - lo)) *
+                      __builtin_amdgcn_rcpf(static_cast<float>(rhi - rlo));
+      next = lo + __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(f)));
+    } else {
+      const float s = static_cast<float>(k - r) * __builtin_amdgcn_rcpf(h.dens);
+      const int step = __builtin_amdgcn_readfirstlane(static_cast<int>(r >= k ? floorf(s)
+                                                                               : ceilf(s)));
+      next = r >= k ? t + min(step, -1) : t + max(step, 1);
+    }
+    t = min(max(next, lo + 1), hi - 1);
   }
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rank_reached<NW>(w, mid, k))
-      hi = mid;
-    else
-      lo = mid;
-  }
+  h.t = hi;
   return hi;
 }
 
@@ -257,6 +317,19 @@ __device__ __forceinline__ void pair_weights(const uint32_t *a, const uint32_t *
   }
 }
 
+// The lane's NW pair weights (Eq. 5), two per dword (P[q] holds pairs 2q in
+// the low half and 2q + 1 in the high half; a lone last pair has 0x7fff
+// beside it, which no threshold counts).
+template <int NW>
+__device__ __forceinline__ void packed_weights(const uint32_t *a, const uint32_t *b,
+                                               uint32_t centre, uint32_t *P) {
+  uint32_t w[NW];
+  pair_weights<NW>(a, b, centre, w);
+#pragma unroll
+  for (int q = 0; q < NW / 2; ++q) P[q] = pack_halves(w[2 * q], w[2 * q + 1]);
+  if constexpr (NW & 1) P[NW / 2] = pack_halves(w[NW - 1], 0x7fffu);
+}
+
 // Stores a lane's NW consecutive bits (NW >= 8) at byte NW / 8 * lane of
 // the pixel's words.
 template <int NW>
@@ -276,12 +349,12 @@ __device__ __forceinline__ void store_lane_bits(uint64_t *out, int lane, const u
 // One pixel of the descriptor and mask.  ap/aq: LDS byte addresses of this
 // lane's samples for the group's first pixel; `shift` (bytes, compile-time
 // after unrolling) moves them to this pixel through the instruction's
-// immediate offset.  out: this pixel's words in desc / mask.  Returns T.
+// immediate offset.  out: this pixel's words in desc / mask.
 template <int NW>
-__device__ __forceinline__ int describe_pixel(const char *lds, const int *ap, const int *aq,
+__device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, const int *aq,
                                               int centre_addr, int shift, int lane, int n,
-                                              int k_eff, int guess, uint64_t *out_desc,
-                                              uint64_t *out_mask) {
+                                              int k_eff, SearchHint &hint,
+                                              uint64_t *out_desc, uint64_t *out_mask) {
   uint32_t a[NW], b[NW];
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
@@ -304,34 +377,37 @@ __device__ __forceinline__ int describe_pixel(const char *lds, const int *ap, co
 #pragma unroll
     for (int j = NW - 1; j >= 0; --j)
       d[j / 32] = __builtin_amdgcn_alignbit(d[j / 32], (b[j] >> 24) - (a[j] >> 24), 31);
-    uint32_t w[NW];
-    pair_weights<NW>(a, b, centre, w);
-    const int T = kth_smallest<NW>(w, k_eff, guess);
-    const uint32_t minus_t1 = static_cast<uint32_t>(-T - 1);
+    uint32_t P[NW / 2];
+    packed_weights<NW>(a, b, centre, P);
+    const uint32_t t1 = static_cast<uint32_t>(kth_smallest<NW / 2>(P, k_eff, 64 * NW, hint) + 1);
+    // halves of P - (T + 1): negative exactly for the pairs with w <= T
 #pragma unroll
-    for (int j = NW - 1; j >= 0; --j)
-      m[j / 32] = __builtin_amdgcn_alignbit(m[j / 32], w[j] + minus_t1, 31);
+    for (int q = NW / 2 - 1; q >= 0; --q) {
+      const uint32_t x = pk_sub16(P[q], t1 | (t1 << 16));
+      m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x, 31);        // pair 2q + 1
+      m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x << 16, 31);  // pair 2q
+    }
     if (NW * lane < n) {
       store_lane_bits<NW>(out_desc, lane, d);
       store_lane_bits<NW>(out_mask, lane, m);
     }
-    return T;
   } else {
     uint32_t d_lo = 0, d_hi = 0, m_lo = 0, m_hi = 0;
     for_words<NW>([&](auto J) {  // Eq. 3
       put_word<J.value>(__ballot((a[J.value] >> 24) > (b[J.value] >> 24)), d_lo, d_hi);
     });
-    uint32_t w[NW];
-    pair_weights<NW>(a, b, centre, w);
-    const int T = kth_smallest<NW>(w, k_eff, guess);
+    constexpr int NP = (NW + 1) / 2;
+    uint32_t P[NP];
+    packed_weights<NW>(a, b, centre, P);
+    const uint32_t T = static_cast<uint32_t>(kth_smallest<NP>(P, k_eff, 64 * NW, hint));
     for_words<NW>([&](auto J) {  // Eq. 6-7
-      put_word<J.value>(__ballot(w[J.value] <= (uint32_t)T), m_lo, m_hi);
+      const uint32_t wj = (J.value & 1) ? P[J.value / 2] >> 16 : P[J.value / 2] & 0xffffu;
+      put_word<J.value>(__ballot(wj <= T), m_lo, m_hi);
     });
     if (lane < n / 64) {
       out_desc[lane] = (static_cast<uint64_t>(d_hi) << 32) | d_lo;
       out_mask[lane] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
     }
-    return T;
   }
 }
 
@@ -404,7 +480,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
   const char *lds = reinterpret_cast<const char *>(tile);
   constexpr int kRowsPerWave = TH / (kDescThreads / 64);
   constexpr int kGroup = 4;  // pixels whose LDS addresses share one base
-  int guess = 64;            // threshold search start: the previous pixel's T
+  SearchHint hint{64, 64.0f * NW / 128.0f};  // the first pixel starts at t = 64
   for (int r = 0;; ++r) {
     int ty;
     if constexpr (PULL_ROWS) {
@@ -431,7 +507,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
       for (int t = 0; t < kGroup; ++t) {
         const int u = u0 + g + t;
         if (u >= W) break;  // uniform
-        guess = describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, n, k_eff, guess,
+        describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, n, k_eff, hint,
                                    desc + ((size_t)v * W + u) * nw,
                                    mask + ((size_t)v * W + u) * nw);
       }
