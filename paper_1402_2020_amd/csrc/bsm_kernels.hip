@@ -185,17 +185,29 @@ __device__ __forceinline__ void for_words(F &&f) {
 // (k - rank) / density from the last probe.  The density (weights per unit
 // of t near T) is a running average over the wave's previous pixels, taken
 // from their first two probes.  The first probe is the previous pixel's T.
+// The steps are scalar integer arithmetic: a division by d <= 4096 is a
+// multiply-high by floor((2^32 - 1) / d) from a constant table.
 constexpr int kTop = 765;  // largest weight: rank(765) counts every weight
 
 // The state carried from one pixel to the next by a wave.
 struct SearchHint {
-  int t;       // previous pixel's T
-  float dens;  // running average of the rank density near T
+  int t;      // previous pixel's T
+  int dens4;  // 4 x the running average of the rank density near T, 1..4096
 };
 
-// A wave-uniform float in a scalar register.
-__device__ __forceinline__ float uniform_f32(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+// floor((2^32 - 1) / d) for d = 1 .. 4096 (entry 0 unused).
+struct RecipTable {
+  uint32_t v[4097];
+  constexpr RecipTable() : v() {
+    v[0] = 0xffffffffu;
+    for (int d = 1; d <= 4096; ++d) v[d] = static_cast<uint32_t>(0xffffffffull / d);
+  }
+};
+__constant__ RecipTable kRecip = RecipTable{};
+
+// About num / den rounded up (within one) for 1 <= den <= 4096; wave-uniform.
+__device__ __forceinline__ int div_up(uint32_t num, int den) {
+  return static_cast<int>(__umulhi(num, kRecip.v[den])) + 1;
 }
 
 // Packs two weights (each <= 765) into the 16-bit halves of a dword.
@@ -245,48 +257,59 @@ __device__ __forceinline__ int wave_rank(const uint32_t *P, int t) {
   return wave_sum(static_cast<int>(lane_rank8<NP>(P, t1 | (t1 << 16)))) >> 3;
 }
 
+// A probe of the search: the bracket lo < T <= hi with rank(lo) < k <=
+// rank(hi) takes in (t, rank(t)).
+struct Bracket {
+  int lo, hi, rlo, rhi;
+  __device__ __forceinline__ void take(int t, int r, int k) {
+    const bool reached = r >= k;
+    hi = reached ? t : hi;
+    rhi = reached ? r : rhi;
+    lo = reached ? lo : t;
+    rlo = reached ? rlo : r;
+  }
+  __device__ __forceinline__ bool open() const { return hi - lo > 1; }
+};
+
+// The next probe after (t, r): the secant through the bracket when both of
+// its ends have been probed, else a step of (k - r) / density from t (at
+// least one), clamped inside the bracket.
+__device__ __forceinline__ int next_probe(const Bracket &b, int t, int r, int k, int dens4) {
+  const bool secant = b.lo >= 0 && b.hi < kTop;
+  const bool down = !secant && r >= k;
+  const int base = secant ? b.lo : t;
+  const uint32_t num = secant ? static_cast<uint32_t>((k - b.rlo) * (b.hi - b.lo))
+                              : 4u * static_cast<uint32_t>(down ? r - k : k - r);
+  const int step = div_up(num, secant ? b.rhi - b.rlo : dens4);
+  const int next = down ? base - step : base + step;
+  return min(max(next, b.lo + 1), b.hi - 1);
+}
+
 // The k-th smallest of the wave's weights (nwts of them), searched from the
 // hint, which is updated for the next pixel.
 template <int NP>
 __device__ __forceinline__ int kth_smallest(const uint32_t *P, int k, int nwts, SearchHint &h) {
-  int lo = -1, hi = kTop, rlo = 0, rhi = nwts;
-  int t = min(max(h.t, 0), kTop - 1);
-  int t0 = -1, r0 = 0;  // the first probe, for the density estimate
-  for (int probe = 0;; ++probe) {
-    const int r = wave_rank<NP>(P, t);
-    if (probe == 0) {
-      t0 = t;
-      r0 = r;
-    } else if (probe == 1) {
-      // rank density between the first two probes (t != t0)
-      const float d = static_cast<float>(r - r0) * __builtin_amdgcn_rcpf(static_cast<float>(t - t0));
-      h.dens = uniform_f32(0.75f * h.dens + 0.25f * fmaxf(d, 0.25f));
+  Bracket b{-1, kTop, 0, nwts};
+  const int t0 = min(max(h.t, 0), kTop - 1);
+  const int r0 = wave_rank<NP>(P, t0);
+  b.take(t0, r0, k);
+  if (b.open()) {
+    const int t1 = next_probe(b, t0, r0, k, h.dens4);
+    const int r1 = wave_rank<NP>(P, t1);
+    b.take(t1, r1, k);
+    // 4 x the rank density between the first two probes, averaged over pixels
+    const int dt = t1 > t0 ? t1 - t0 : t0 - t1;
+    const int d4 = div_up(4u * static_cast<uint32_t>(r1 > r0 ? r1 - r0 : r0 - r1), dt);
+    h.dens4 = min((3 * h.dens4 + d4) >> 2, 4096);
+    int t = t1, r = r1;
+    while (b.open()) {
+      t = next_probe(b, t, r, k, h.dens4);
+      r = wave_rank<NP>(P, t);
+      b.take(t, r, k);
     }
-    if (r >= k) {
-      hi = t;
-      rhi = r;
-    } else {
-      lo = t;
-      rlo = r;
-    }
-    if (hi - lo <= 1) break;
-    int next;
-    if (lo >= 0 && hi < kTop) {
-      // secant through the bracket: where the line from (lo, rlo) to
-      // (hi, rhi) reaches k
-      const float f = static_cast<float>((k - rlo) * (hi - lo)) *
-                      __builtin_amdgcn_rcpf(static_cast<float>(rhi - rlo));
-      next = lo + __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(f)));
-    } else {
-      const float s = static_cast<float>(k - r) * __builtin_amdgcn_rcpf(h.dens);
-      const int step = __builtin_amdgcn_readfirstlane(static_cast<int>(r >= k ? floorf(s)
-                                                                               : ceilf(s)));
-      next = r >= k ? t + min(step, -1) : t + max(step, 1);
-    }
-    t = min(max(next, lo + 1), hi - 1);
   }
-  h.t = hi;
-  return hi;
+  h.t = b.hi;
+  return b.hi;
 }
 
 // Pair weights of Eq. 5: max of the CIELAB SADs of the two samples to the
@@ -377,6 +400,10 @@ __device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, c
 #pragma unroll
     for (int j = NW - 1; j >= 0; --j)
       d[j / 32] = __builtin_amdgcn_alignbit(d[j / 32], (b[j] >> 24) - (a[j] >> 24), 31);
+    // Keep the descriptor bits here: otherwise the compiler computes them at
+    // the store, after the search, and the samples stay live through it.
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) asm volatile("" : "+v"(d[r]));
     uint32_t P[NW / 2];
     packed_weights<NW>(a, b, centre, P);
     const uint32_t t1 = static_cast<uint32_t>(kth_smallest<NW / 2>(P, k_eff, 64 * NW, hint) + 1);
@@ -417,6 +444,33 @@ struct DescribeConsts {
   int nw, radius, pitch, k;
 };
 
+// Byte offsets in the LDS tile, relative to the centre, of this lane's pair
+// samples (0 for padded pairs).  They depend only on the lane and the tile
+// pitch, so a persistent kernel computes them once.
+template <int NW>
+struct PairOffsets {
+  int p[NW], q[NW];
+};
+
+template <int NW>
+__device__ __forceinline__ void pair_offsets(const DescribeConsts &c, int lane,
+                                             PairOffsets<NW> &o) {
+  const int n = 64 * c.nw;
+  const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
+  // (loads without a branch, so that all of them are in flight at once)
+  int32_t pe[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) pe[j] = pat32[min(pair_of<NW>(lane, j), n - 1)];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int32_t e = pair_of<NW>(lane, j) < n ? pe[j] : 0;
+    const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
+    const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
+    o.p[j] = 4 * (py * c.pitch + px);
+    o.q[j] = 4 * (qy * c.pitch + qx);
+  }
+}
+
 // Rows of the tile go to the waves either fixed (TH / 4 consecutive rows
 // each) or, with PULL_ROWS, one at a time from the LDS counter *row_next as
 // the waves become free: a wave whose pixels needed fewer search probes then
@@ -426,6 +480,7 @@ template <int NW, int TW, int TH, bool PULL_ROWS>
 __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next,
                                                    const uint32_t *__restrict__ packed, int W,
                                                    int H, const DescribeConsts &c,
+                                                   const PairOffsets<NW> &off,
                                                    uint64_t *__restrict__ desc,
                                                    uint64_t *__restrict__ mask, int u0, int v0) {
   const int radius = c.radius, pitch = c.pitch, nw = c.nw, n = 64 * nw;
@@ -457,22 +512,6 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // Byte offsets in LDS, relative to the centre, of this lane's pair samples
-  // (0 for padded pairs).
-  int offp[NW], offq[NW];
-  const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
-#pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    offp[j] = offq[j] = 0;
-    const int i = pair_of<NW>(lane, j);
-    if (i < n) {
-      const int32_t e = pat32[i];
-      const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
-      const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
-      offp[j] = 4 * (py * pitch + px);
-      offq[j] = 4 * (qy * pitch + qx);
-    }
-  }
   const int k_eff = c.k + (64 * NW - n);
   if (PULL_ROWS && threadIdx.x == 0) *row_next = 0;
   __syncthreads();
@@ -480,7 +519,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
   const char *lds = reinterpret_cast<const char *>(tile);
   constexpr int kRowsPerWave = TH / (kDescThreads / 64);
   constexpr int kGroup = 4;  // pixels whose LDS addresses share one base
-  SearchHint hint{64, 64.0f * NW / 128.0f};  // the first pixel starts at t = 64
+  SearchHint hint{64, NW * 2};  // the first pixel starts at t = 64, density n / 128
   for (int r = 0;; ++r) {
     int ty;
     if constexpr (PULL_ROWS) {
@@ -500,8 +539,8 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
       int ap[NW], aq[NW];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        ap[j] = c0 + offp[j];
-        aq[j] = c0 + offq[j];
+        ap[j] = c0 + off.p[j];
+        aq[j] = c0 + off.q[j];
       }
 #pragma unroll
       for (int t = 0; t < kGroup; ++t) {
@@ -520,7 +559,9 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
-  describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, desc, mask,
+  PairOffsets<NW> off;
+  pair_offsets<NW>(c, threadIdx.x & 63, off);
+  describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, off, desc, mask,
                                         blockIdx.x * TW, blockIdx.y * TH);
 }
 
@@ -1672,6 +1713,8 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
   __shared__ int slot, row_next;
   const int n = bw->npairs;
   const bool right_first = blockIdx.x % right_every == 0;
+  PairOffsets<NW> off;
+  pair_offsets<NW>(cm, threadIdx.x & 63, off);
   for (int phase = 0; phase < 2; ++phase) {
     if ((phase == 0) == right_first) {
       const int *start = bw->start + kQueueDescribe * (n + 1);
@@ -1687,8 +1730,9 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
         // view 0 is the right view; view 1 (mask off only) the left view
         describe_right_tile<kRightPx>(reinterpret_cast<uint8_t *>(dlds),
                                       uniform(view ? p.packedL : p.packedR), W, H, cr,
-                                      uniform(view ? p.descL : p.descR), (tile % tx) * kRightTW,
-                                      (tile / tx) * kRightTH);
+                                      uniform(view ? p.descL : p.descR),
+                                      uniform((tile % tx) * kRightTW),
+                                      uniform((tile / tx) * kRightTH));
       }
     } else {
       const int *start = bw->start + kQueueDescribeMask * (n + 1);
@@ -1701,9 +1745,10 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
         const int W = uniform(p.W), H = uniform(p.H);
         const int tx = (W + TW - 1) / TW;
         const int local = t - start[i];
-        describe_mask_tile<NW, TW, TH, true>(dlds, &row_next, uniform(p.packedL), W, H, cm,
+        describe_mask_tile<NW, TW, TH, true>(dlds, &row_next, uniform(p.packedL), W, H, cm, off,
                                              uniform(p.descL), uniform(p.maskL),
-                                             (local % tx) * TW, (local / tx) * TH);
+                                             uniform((local % tx) * TW),
+                                             uniform((local / tx) * TH));
       }
     }
   }
