@@ -588,6 +588,7 @@ constexpr int kRightTW = 64 * kRightPx, kRightTH = 4, kRightThreads = 256;
 constexpr int kRightGroup = 16;                     // words per pass (one pixel per lane)
 constexpr int kDescRightEvery = 4;  // batch: one describe workgroup in this many starts right
 constexpr int kRightStageWords = 2;                 // words per LDS stage (four per lane)
+constexpr int kRightRegWords = 8;  // words per pass in registers (four per lane, nw % 8 == 0)
 // Images with fewer wide tiles than this run one pixel per lane (64-pixel
 // tiles), which gives four times as many workgroups.
 constexpr int kRightWideMinBlocks = 1024;
@@ -620,6 +621,26 @@ __device__ __forceinline__ uint32_t tile_bytes(const uint8_t *tile, int a, int o
     const uint32_t *w = reinterpret_cast<const uint32_t *>(tile + a + (o & ~3));
     return __builtin_amdgcn_alignbyte(w[1], w[0], static_cast<uint32_t>(o & 3));
   }
+}
+
+// An int2 table read through the constant address space: the table is
+// never written while a kernel runs and its indices are wave-uniform, so
+// every read is a scalar load, also where descriptor stores share the loop.
+struct ConstInt2Table {
+  const int2 *p;
+  __device__ __forceinline__ int2 operator[](int i) const {
+    const __attribute__((address_space(4))) long long *q =
+        (const __attribute__((address_space(4))) long long *)p;
+    const long long v = q[i];
+    return make_int2(static_cast<int>(v), static_cast<int>(v >> 32));
+  }
+};
+
+// Bytes x + 0 .. x + 3 for the lane whose first pixel sits at the 4-byte
+// aligned LDS address lp, at tile offset o: two dwords and a funnel shift.
+__device__ __forceinline__ uint32_t lane_bytes4(const uint8_t *lp, int o) {
+  const uint32_t *w = reinterpret_cast<const uint32_t *>(lp + (o & ~3));
+  return __builtin_amdgcn_alignbyte(w[1], w[0], static_cast<uint32_t>(o & 3));
 }
 
 template <int PX>
@@ -664,7 +685,7 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
   if (v >= H) return;                // no barrier follows in this tile
   const int base = (ty + radius) * pitch + hx + PX * lane;  // multiple of 4 for PX = 4
   const int px0 = u0 + PX * lane;                           // the lane's first pixel
-  const int2 *__restrict__ offs = c.offs;
+  const ConstInt2Table offs{c.offs};
   if constexpr (PX == 1) {
     uint64_t *out = desc + ((size_t)v * W + px0) * nw;
     if (nw % kRightGroup == 0) {
@@ -736,6 +757,47 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
       }
     }
   } else {
+    if (nw % kRightRegWords == 0) {
+      // Eight words (64 bytes) of each of the lane's four pixels in
+      // registers, then each pixel's 64 bytes as four 16-byte stores in a
+      // row: the half-lines are complete when they leave, so no partly
+      // written line waits in the cache for the rest of the pixel's string.
+      const uint8_t *lp = itile + base;  // the lane's first pixel, 4-byte aligned
+      uint64_t *out = desc + ((size_t)v * W + px0) * nw;
+      for (int g0 = 0; g0 < nw; g0 += kRightRegWords) {
+        uint32_t words[kRightRegWords][2][PX];
+        for_words<kRightRegWords>([&](auto J) {
+          constexpr int jj = J.value;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            uint32_t acc[PX] = {};
+#pragma unroll 8
+            for (int b = 31; b >= 0; --b) {
+              const int2 o = offs[64 * (g0 + jj) + 32 * h + b];  // uniform: scalar load
+              const uint32_t P = lane_bytes4(lp, o.x), Q = lane_bytes4(lp, o.y);
+#pragma unroll
+              for (int k = 0; k < PX; ++k) {
+                const uint32_t diff = ((Q >> (8 * k)) & 0xffu) - ((P >> (8 * k)) & 0xffu);
+                acc[k] = __builtin_amdgcn_alignbit(acc[k], diff, 31);
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < PX; ++k) words[jj][h][k] = acc[k];
+          }
+        });
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          if (px0 + k < W) {
+            uint4 *dst = reinterpret_cast<uint4 *>(out + (size_t)k * nw + g0);
+#pragma unroll
+            for (int q = 0; q < kRightRegWords / 2; ++q)
+              dst[q] = make_uint4(words[2 * q][0][k], words[2 * q][1][k], words[2 * q + 1][0][k],
+                                  words[2 * q + 1][1][k]);
+          }
+        }
+      }
+      return;
+    }
     uint64_t *stage = stage_all + wave * kRightStageWords * TW;
     const int valid = min(TW, W - u0);  // pixels of this tile inside the image
     uint64_t *row_out = desc + ((size_t)v * W + u0) * nw;
@@ -1685,10 +1747,10 @@ __global__ __launch_bounds__(kColorThreads) void k_batch_color(const BatchWork *
                                                                Mq mq, int use_mask) {
   __shared__ int slot;
   const int *start = bw->start + kQueueColor * (bw->npairs + 1);
-  WgQueue qu{bw->counters + kQueueColor * kCounterStride, start[bw->npairs], &slot, -1};
+  WgQueue qu{bw->counters + kQueueColor * kCounterStride, uniform(start[bw->npairs]), &slot, -1};
   for (int t = qu.first(false); t < qu.total; t = qu.next()) {
     qu.begin(t);
-    const int i = owner(start, bw->npairs, t);
+    const int i = uniform(owner(start, bw->npairs, t));
     const BatchPair &p = bw->pairs[bw->order[i]];
     const int tx = (p.W + kColorTX - 1) / kColorTX;
     const int ty = (p.H + kBatchColorTY - 1) / kBatchColorTY;
@@ -1713,16 +1775,14 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
   __shared__ int slot, row_next;
   const int n = bw->npairs;
   const bool right_first = blockIdx.x % right_every == 0;
-  PairOffsets<NW> off;
-  pair_offsets<NW>(cm, threadIdx.x & 63, off);
   for (int phase = 0; phase < 2; ++phase) {
     if ((phase == 0) == right_first) {
       const int *start = bw->start + kQueueDescribe * (n + 1);
-      WgQueue qu{bw->counters + kQueueDescribe * kCounterStride, start[n], &slot, -1};
+      WgQueue qu{bw->counters + kQueueDescribe * kCounterStride, uniform(start[n]), &slot, -1};
       if (qu.total == 0) continue;
       for (int t = qu.first(phase == 1); t < qu.total; t = qu.next()) {
         qu.begin(t);
-        const int i = owner(start, n, t);
+        const int i = uniform(owner(start, n, t));
         const BatchPair &p = bw->pairs[bw->order[i]];
         const int W = uniform(p.W), H = uniform(p.H);
         const int tx = (W + kRightTW - 1) / kRightTW, ty = (H + kRightTH - 1) / kRightTH;
@@ -1736,15 +1796,18 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
       }
     } else {
       const int *start = bw->start + kQueueDescribeMask * (n + 1);
-      WgQueue qu{bw->counters + kQueueDescribeMask * kCounterStride, start[n], &slot, -1};
+      WgQueue qu{bw->counters + kQueueDescribeMask * kCounterStride, uniform(start[n]), &slot, -1};
       if (qu.total == 0) continue;
       for (int t = qu.first(phase == 1); t < qu.total; t = qu.next()) {
         qu.begin(t);
-        const int i = owner(start, n, t);
+        const int i = uniform(owner(start, n, t));
         const BatchPair &p = bw->pairs[bw->order[i]];
         const int W = uniform(p.W), H = uniform(p.H);
         const int tx = (W + TW - 1) / TW;
         const int local = t - start[i];
+        // per tile, so that they hold no registers during descriptor-only tiles
+        PairOffsets<NW> off;
+        pair_offsets<NW>(cm, threadIdx.x & 63, off);
         describe_mask_tile<NW, TW, TH, true>(dlds, &row_next, uniform(p.packedL), W, H, cm, off,
                                              uniform(p.descL), uniform(p.maskL),
                                              uniform((local % tx) * TW),
