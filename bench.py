@@ -303,8 +303,10 @@ def bench_serve(args):
     sigma = 4.0 * S / 26
     specs = synth.batch_specs(64)
     t0 = time.perf_counter()
-    scenes = [synth.batch_scene(s) for s in specs]
+    scenes = batch_scenes(specs)
     gen_s = time.perf_counter() - t0
+    print(json.dumps({"progress": "scenes", "pairs": len(scenes), "seconds": round(gen_s, 1)}),
+          flush=True)
     pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
     ctx = _bsm.Context(n, S, sigma, pattern=pat, device=0)
     ctx.serve_config(32 << 30, 1 << 16, args.max_group)
