@@ -442,45 +442,101 @@ __device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, c
 struct DescribeConsts {
   const int8_t *pattern;  // [n][4]
   int nw, radius, pitch, k;
+  int table_off;  // single-pair kernel: LDS byte offset of the pair-offset table
 };
 
-// Byte offsets in the LDS tile, relative to the centre, of this lane's pair
-// samples (0 for padded pairs).  They depend only on the lane and the tile
-// pitch, so a persistent kernel computes them once.
+// The pair-offset table in LDS: for lane l and slot j, the byte offsets in
+// the tile, relative to the centre, of the pair's two samples (0 for padded
+// pairs), as int2 at ((j / 2) * 64 + l) * 2 + j % 2, so that a lane reads two
+// slots with one 16-byte load and the 64 lanes read 1 KB without bank
+// conflicts.  The offsets depend only on the lane and the tile pitch: one
+// wave writes the table once per launch and every wave of the workgroup
+// reads it, which keeps them out of the registers.
 template <int NW>
-struct PairOffsets {
-  int p[NW], q[NW];
-};
+__host__ __device__ constexpr int pair_table_bytes() {
+  return ((NW + 1) / 2) * 64 * 16;
+}
 
 template <int NW>
-__device__ __forceinline__ void pair_offsets(const DescribeConsts &c, int lane,
-                                             PairOffsets<NW> &o) {
-  const int n = 64 * c.nw;
+__device__ __forceinline__ void write_pair_table(const DescribeConsts &c, int2 *tab) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x, n = 64 * c.nw;
   const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
-  // (loads without a branch, so that all of them are in flight at once)
-  int32_t pe[NW];
-#pragma unroll
-  for (int j = 0; j < NW; ++j) pe[j] = pat32[min(pair_of<NW>(lane, j), n - 1)];
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
-    const int32_t e = pair_of<NW>(lane, j) < n ? pe[j] : 0;
+    const int i = pair_of<NW>(lane, j);
+    const int32_t e = i < n ? pat32[i] : 0;
     const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
     const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
-    o.p[j] = 4 * (py * c.pitch + px);
-    o.q[j] = 4 * (qy * c.pitch + qx);
+    tab[((j >> 1) * 64 + lane) * 2 + (j & 1)] =
+        make_int2(4 * (py * c.pitch + px), 4 * (qy * c.pitch + qx));
   }
 }
+
+// Where a wave finds its lanes' pair offsets: TableOffsets reads the LDS
+// table per group of pixels (registers free for a fifth wave per SIMD);
+// RegOffsets holds them in 2 NW registers (no LDS load before the gathers,
+// which matters where descriptor-only tiles keep the LDS busy).
+template <int NW>
+struct TableOffsets {
+  const int2 *tab;
+  // ap[j] / aq[j] = c0 + the offsets of slot j for this lane
+  __device__ __forceinline__ void addresses(int c0, int lane, int *ap, int *aq) const {
+    if constexpr (NW == 1) {
+      const int2 e = tab[2 * lane];
+      ap[0] = c0 + e.x;
+      aq[0] = c0 + e.y;
+    } else {
+#pragma unroll
+      for (int j = 0; j < NW; j += 2) {
+        const int4 e = *reinterpret_cast<const int4 *>(tab + ((j >> 1) * 64 + lane) * 2);
+        ap[j] = c0 + e.x;
+        aq[j] = c0 + e.y;
+        ap[j + 1] = c0 + e.z;
+        aq[j + 1] = c0 + e.w;
+      }
+    }
+  }
+};
+
+template <int NW>
+struct RegOffsets {
+  int p[NW], q[NW];
+  __device__ __forceinline__ RegOffsets(const DescribeConsts &c, int lane) {
+    const int n = 64 * c.nw;
+    const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
+    // (loads without a branch, so that all of them are in flight at once)
+    int32_t pe[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) pe[j] = pat32[min(pair_of<NW>(lane, j), n - 1)];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int32_t e = pair_of<NW>(lane, j) < n ? pe[j] : 0;
+      const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
+      const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
+      p[j] = 4 * (py * c.pitch + px);
+      q[j] = 4 * (qy * c.pitch + qx);
+    }
+  }
+  __device__ __forceinline__ void addresses(int c0, int, int *ap, int *aq) const {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      ap[j] = c0 + p[j];
+      aq[j] = c0 + q[j];
+    }
+  }
+};
 
 // Rows of the tile go to the waves either fixed (TH / 4 consecutive rows
 // each) or, with PULL_ROWS, one at a time from the LDS counter *row_next as
 // the waves become free: a wave whose pixels needed fewer search probes then
 // takes another row instead of waiting at the next barrier of a persistent
 // kernel for the others.
-template <int NW, int TW, int TH, bool PULL_ROWS>
+template <int NW, int TW, int TH, bool PULL_ROWS, typename Offsets>
 __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next,
                                                    const uint32_t *__restrict__ packed, int W,
                                                    int H, const DescribeConsts &c,
-                                                   const PairOffsets<NW> &off,
+                                                   const Offsets &off,
                                                    uint64_t *__restrict__ desc,
                                                    uint64_t *__restrict__ mask, int u0, int v0) {
   const int radius = c.radius, pitch = c.pitch, nw = c.nw, n = 64 * nw;
@@ -537,11 +593,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
       if (u0 + g >= W) break;  // uniform
       const int c0 = 4 * ((ty + radius) * pitch + (g + radius));
       int ap[NW], aq[NW];
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        ap[j] = c0 + off.p[j];
-        aq[j] = c0 + off.q[j];
-      }
+      off.addresses(c0, lane, ap, aq);
 #pragma unroll
       for (int t = 0; t < kGroup; ++t) {
         const int u = u0 + g + t;
@@ -559,10 +611,10 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
-  PairOffsets<NW> off;
-  pair_offsets<NW>(c, threadIdx.x & 63, off);
-  describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, off, desc, mask,
-                                        blockIdx.x * TW, blockIdx.y * TH);
+  int2 *tab = reinterpret_cast<int2 *>(reinterpret_cast<char *>(tile) + c.table_off);
+  write_pair_table<NW>(c, tab);  // the tile function's first barrier publishes it
+  describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, TableOffsets<NW>{tab},
+                                        desc, mask, blockIdx.x * TW, blockIdx.y * TH);
 }
 
 // ===========================================================================
@@ -1805,9 +1857,9 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
         const int W = uniform(p.W), H = uniform(p.H);
         const int tx = (W + TW - 1) / TW;
         const int local = t - start[i];
-        // per tile, so that they hold no registers during descriptor-only tiles
-        PairOffsets<NW> off;
-        pair_offsets<NW>(cm, threadIdx.x & 63, off);
+        // offsets in registers, per tile, so that they hold none during
+        // descriptor-only tiles
+        const RegOffsets<NW> off(cm, threadIdx.x & 63);
         describe_mask_tile<NW, TW, TH, true>(dlds, &row_next, uniform(p.packedL), W, H, cm, off,
                                              uniform(p.descL), uniform(p.maskL),
                                              uniform((local % tx) * TW),
@@ -1922,16 +1974,19 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
 // Launchers
 // ===========================================================================
 DescribeConsts describe_consts(const DeviceTables &t) {
-  return DescribeConsts{t.pattern, t.nw, t.radius, t.left_pitch_for(t.tune.desc_tile_w), t.k};
+  return DescribeConsts{t.pattern, t.nw, t.radius, t.left_pitch_for(t.tune.desc_tile_w), t.k, 0};
 }
 
 RightConsts right_consts(const DeviceTables &t) {
   return RightConsts{t.right_offs, t.n, t.nw, t.radius, t.right_pitch};
 }
 
-size_t mask_lds_bytes(const DeviceTables &t, int tw, int th = kDescTH) {
+// LDS of a describe+mask tile (TH + 2 radius rows at the tile pitch).
+size_t mask_tile_bytes(const DeviceTables &t, int tw, int th) {
   return (size_t)(th + 2 * t.radius) * t.left_pitch_for(tw) * sizeof(uint32_t);
 }
+
+size_t round16(size_t x) { return (x + 15) / 16 * 16; }
 
 template <int NW, int TW>
 hipError_t launch_describe_mask_t(const uint32_t *packed, int W, int H, const DeviceTables &t,
@@ -1941,15 +1996,16 @@ hipError_t launch_describe_mask_t(const uint32_t *packed, int W, int H, const De
   const long long tall_tiles = (long long)((W + TW - 1) / TW) * ((H + kDescTH - 1) / kDescTH);
   const bool tall = t.tune.pair_desc_th ? t.tune.pair_desc_th == kDescTH
                                         : tall_tiles >= kDescTallMinTiles;
-  if (tall) {
-    dim3 grid((W + TW - 1) / TW, (H + kDescTH - 1) / kDescTH);
-    hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTH>), grid, dim3(kDescThreads),
-                       mask_lds_bytes(t, TW, kDescTH), s, packed, W, H, c, desc, mask);
-  } else {
-    dim3 grid((W + TW - 1) / TW, (H + kDescTHSmall - 1) / kDescTHSmall);
-    hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTHSmall>), grid, dim3(kDescThreads),
-                       mask_lds_bytes(t, TW, kDescTHSmall), s, packed, W, H, c, desc, mask);
-  }
+  const int th = tall ? kDescTH : kDescTHSmall;
+  c.table_off = static_cast<int>(round16(mask_tile_bytes(t, TW, th)));
+  const size_t lds = c.table_off + pair_table_bytes<NW>();
+  dim3 grid((W + TW - 1) / TW, (H + th - 1) / th);
+  if (tall)
+    hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTH>), grid, dim3(kDescThreads), lds, s,
+                       packed, W, H, c, desc, mask);
+  else
+    hipLaunchKernelGGL((k_describe_mask<NW, TW, kDescTHSmall>), grid, dim3(kDescThreads), lds,
+                       s, packed, W, H, c, desc, mask);
   return hipGetLastError();
 }
 
@@ -2066,7 +2122,7 @@ hipError_t launch_batch_t(const BatchLaunch &bl, const DeviceTables &t, int use_
     if (attr != hipSuccess) return attr;
     DescribeConsts cm = describe_consts(t);
     cm.pitch = t.left_pitch_for(TW);
-    const size_t lds = std::max(mask_lds_bytes(t, TW, TH),
+    const size_t lds = std::max(mask_tile_bytes(t, TW, TH),
                                 right_lds_bytes(kRightPx, t.radius, t.right_pitch));
     const int g1 = persistent_grid(k_batch_describe<NW, TW, TH>, kDescThreads, lds,
                                    tu.blocks_per_cu[1]);
