@@ -247,6 +247,14 @@ def bench_batch(args):
     # The same 64 pairs at a quarter of the size (W 80-480, H 60-270, dmax
     # 8-64): launch-bound pairs, where one persistent launch for all of them
     # pays off.  Reported beside, not as the value.
+    if args.no_quarter:
+        ctx.close()
+        if not args.no_cpu_baseline:
+            import oracle
+            opat = oracle.make_pattern(synth.PATTERN_SEED, n, S, sigma)
+            out["cpu_baseline"] = batch_cpu_baseline(scenes, opat, n)
+        print(json.dumps(out), flush=True)
+        return
     small = batch_scenes(specs, scale=0.25)
     s_items = [(torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), sc.dmax)
                for sc in small]
@@ -627,6 +635,9 @@ def main():
                     help="workload (default 3: the 64 uneven pairs, the largest one-GPU "
                          "workload); 0-2 single pairs, 4 serving, 5 n-sweep, 6 radiometric")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-quarter", action="store_true",
+                    help="batch workload: skip the quarter-size comparison (profiler runs, so "
+                         "that every batch kernel dispatch is a full-size one)")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_1402_2020_amd",
                                                            "tuning_cache.json"),
                     help="batch workload: the autotuner's persistent cache (a hit skips the "
