@@ -205,9 +205,18 @@ struct RecipTable {
 };
 __constant__ RecipTable kRecip = RecipTable{};
 
-// About num / den rounded up (within one) for 1 <= den <= 4096; wave-uniform.
+// About num / den rounded up (within one) for 1 <= den <= 4096 and
+// num < 2^24; wave-uniform.  kShortChain: from v_rcp_f32 instead of the
+// table, for kernels too short to hide a scalar load per probe (few
+// weights a lane: few waves, few probes' worth of work between loads).
+template <bool kShortChain>
 __device__ __forceinline__ int div_up(uint32_t num, int den) {
-  return static_cast<int>(__umulhi(num, kRecip.v[den])) + 1;
+  if constexpr (kShortChain)
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(
+               static_cast<float>(num) * __builtin_amdgcn_rcpf(static_cast<float>(den)))) +
+           1;
+  else
+    return static_cast<int>(__umulhi(num, kRecip.v[den])) + 1;
 }
 
 // Packs two weights (each <= 765) into the 16-bit halves of a dword.
@@ -251,10 +260,22 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // #{w <= t} over the wave's packed weights (t wave-uniform, 0 <= t < 765).
+// With at most four weights a lane (n <= 256) ballots and scalar popcounts
+// make the shorter chain; with more, the vector count and DPP sum.
 template <int NP>
 __device__ __forceinline__ int wave_rank(const uint32_t *P, int t) {
-  const uint32_t t1 = static_cast<uint32_t>(t + 1);
-  return wave_sum(static_cast<int>(lane_rank8<NP>(P, t1 | (t1 << 16)))) >> 3;
+  if constexpr (NP <= 2) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      c += __popcll(__ballot((P[q] & 0xffffu) <= static_cast<uint32_t>(t)));
+      c += __popcll(__ballot((P[q] >> 16) <= static_cast<uint32_t>(t)));
+    }
+    return c;
+  } else {
+    const uint32_t t1 = static_cast<uint32_t>(t + 1);
+    return wave_sum(static_cast<int>(lane_rank8<NP>(P, t1 | (t1 << 16)))) >> 3;
+  }
 }
 
 // A probe of the search: the bracket lo < T <= hi with rank(lo) < k <=
@@ -274,36 +295,88 @@ struct Bracket {
 // The next probe after (t, r): the secant through the bracket when both of
 // its ends have been probed, else a step of (k - r) / density from t (at
 // least one), clamped inside the bracket.
+template <bool kShortChain>
 __device__ __forceinline__ int next_probe(const Bracket &b, int t, int r, int k, int dens4) {
   const bool secant = b.lo >= 0 && b.hi < kTop;
   const bool down = !secant && r >= k;
   const int base = secant ? b.lo : t;
   const uint32_t num = secant ? static_cast<uint32_t>((k - b.rlo) * (b.hi - b.lo))
                               : 4u * static_cast<uint32_t>(down ? r - k : k - r);
-  const int step = div_up(num, secant ? b.rhi - b.rlo : dens4);
+  const int step = div_up<kShortChain>(num, secant ? b.rhi - b.rlo : dens4);
   const int next = down ? base - step : base + step;
   return min(max(next, b.lo + 1), b.hi - 1);
 }
 
 // The k-th smallest of the wave's weights (nwts of them), searched from the
 // hint, which is updated for the next pixel.
+// The same search for lanes with at most four weights (n <= 256), where a
+// probe is a few ballots: galloping from the hint in steps of 8, 16, ...
+// until T is bracketed, then bisection.  Each step is one scalar add, which
+// beats the secant's longer chain of scalar and vector work per probe when
+// the kernel has few waves to overlap.
+template <int NP>
+__device__ __forceinline__ int kth_smallest_gallop(const uint32_t *P, int k, SearchHint &h) {
+  int lo, hi;  // rank not reached at lo, reached at hi
+  const int g = min(max(h.t, 0), kTop - 1);
+  if (wave_rank<NP>(P, g) >= k) {
+    hi = g;
+    for (int step = 8;; step <<= 1) {
+      const int t = hi - step;
+      if (t < 0) {
+        lo = -1;
+        break;
+      }
+      if (wave_rank<NP>(P, t) < k) {
+        lo = t;
+        break;
+      }
+      hi = t;
+    }
+  } else {
+    lo = g;
+    for (int step = 8;; step <<= 1) {
+      const int t = lo + step;
+      if (t >= kTop) {
+        hi = kTop;
+        break;
+      }
+      if (wave_rank<NP>(P, t) >= k) {
+        hi = t;
+        break;
+      }
+      lo = t;
+    }
+  }
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (wave_rank<NP>(P, mid) >= k)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  h.t = hi;
+  return hi;
+}
+
 template <int NP>
 __device__ __forceinline__ int kth_smallest(const uint32_t *P, int k, int nwts, SearchHint &h) {
+  if constexpr (NP <= 2) return kth_smallest_gallop<NP>(P, k, h);
+  constexpr bool kShort = false;
   Bracket b{-1, kTop, 0, nwts};
   const int t0 = min(max(h.t, 0), kTop - 1);
   const int r0 = wave_rank<NP>(P, t0);
   b.take(t0, r0, k);
   if (b.open()) {
-    const int t1 = next_probe(b, t0, r0, k, h.dens4);
+    const int t1 = next_probe<kShort>(b, t0, r0, k, h.dens4);
     const int r1 = wave_rank<NP>(P, t1);
     b.take(t1, r1, k);
     // 4 x the rank density between the first two probes, averaged over pixels
     const int dt = t1 > t0 ? t1 - t0 : t0 - t1;
-    const int d4 = div_up(4u * static_cast<uint32_t>(r1 > r0 ? r1 - r0 : r0 - r1), dt);
+    const int d4 = div_up<kShort>(4u * static_cast<uint32_t>(r1 > r0 ? r1 - r0 : r0 - r1), dt);
     h.dens4 = min((3 * h.dens4 + d4) >> 2, 4096);
     int t = t1, r = r1;
     while (b.open()) {
-      t = next_probe(b, t, r, k, h.dens4);
+      t = next_probe<kShort>(b, t, r, k, h.dens4);
       r = wave_rank<NP>(P, t);
       b.take(t, r, k);
     }
@@ -611,10 +684,18 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
-  int2 *tab = reinterpret_cast<int2 *>(reinterpret_cast<char *>(tile) + c.table_off);
-  write_pair_table<NW>(c, tab);  // the tile function's first barrier publishes it
-  describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, TableOffsets<NW>{tab},
-                                        desc, mask, blockIdx.x * TW, blockIdx.y * TH);
+  if constexpr (NW >= 16) {
+    // 4 NW offset registers would cap the kernel at four waves per SIMD
+    int2 *tab = reinterpret_cast<int2 *>(reinterpret_cast<char *>(tile) + c.table_off);
+    write_pair_table<NW>(c, tab);  // the tile function's first barrier publishes it
+    describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, TableOffsets<NW>{tab},
+                                          desc, mask, blockIdx.x * TW, blockIdx.y * TH);
+  } else {
+    // few offsets: in registers, so that no LDS load precedes the gathers
+    describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c,
+                                          RegOffsets<NW>(c, threadIdx.x & 63), desc, mask,
+                                          blockIdx.x * TW, blockIdx.y * TH);
+  }
 }
 
 // ===========================================================================
@@ -695,7 +776,10 @@ __device__ __forceinline__ uint32_t lane_bytes4(const uint8_t *lp, int o) {
   return __builtin_amdgcn_alignbyte(w[1], w[0], static_cast<uint32_t>(o & 3));
 }
 
-template <int PX>
+// kWhole: the words come in whole register groups (nw a multiple of
+// kRightGroup for PX = 1, of kRightRegWords for PX = 4); the other case has
+// a kernel of its own, so that neither shapes the other's code.
+template <int PX, bool kWhole>
 __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
                                                     const uint32_t *__restrict__ packed, int W,
                                                     int H, const RightConsts &c,
@@ -740,7 +824,7 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
   const ConstInt2Table offs{c.offs};
   if constexpr (PX == 1) {
     uint64_t *out = desc + ((size_t)v * W + px0) * nw;
-    if (nw % kRightGroup == 0) {
+    if constexpr (kWhole) {
       // Whole groups (n a multiple of 1024): word indices are compile-time
       // constants and no word is skipped, so the 32 accumulators stay in
       // registers and leave as eight 16-byte stores.
@@ -780,7 +864,10 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
           acc[jj][h] = 0;
 #pragma unroll 8
           for (int b = 31; b >= 0; --b) {
-            const int2 o = offs[64 * (g0 + jj) + 32 * h + b];  // uniform: scalar load
+            // (a plain load: in this loop, with its early exit, vector loads
+            // of the same address by every lane run further ahead than
+            // scalar ones)
+            const int2 o = c.offs[64 * (g0 + jj) + 32 * h + b];
             // tau of Eq. 3: for bytes p, q the difference q - p has bit 31
             // set exactly when p > q; alignbit shifts that bit into acc.
             const uint32_t diff = tile_bytes<1>(itile, base, o.y) - tile_bytes<1>(itile, base, o.x);
@@ -809,7 +896,7 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
       }
     }
   } else {
-    if (nw % kRightRegWords == 0) {
+    if constexpr (kWhole) {
       // Eight words (64 bytes) of each of the lane's four pixels in
       // registers, then each pixel's 64 bytes as four 16-byte stores in a
       // row: the half-lines are complete when they leave, so no partly
@@ -893,13 +980,13 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
   }
 }
 
-template <int PX>
+template <int PX, bool kWhole>
 __global__ __launch_bounds__(kRightThreads) void k_describe_right(
     const uint32_t *__restrict__ packed, int W, int H, RightConsts c,
     uint64_t *__restrict__ desc) {
   extern __shared__ uint8_t rlds[];
-  describe_right_tile<PX>(rlds, packed, W, H, c, desc, blockIdx.x * 64 * PX,
-                          blockIdx.y * kRightTH);
+  describe_right_tile<PX, kWhole>(rlds, packed, W, H, c, desc, blockIdx.x * 64 * PX,
+                                  blockIdx.y * kRightTH);
 }
 
 // ===========================================================================
@@ -1840,7 +1927,7 @@ __global__ __launch_bounds__(kDescThreads, 4) void k_batch_describe(
         const int tx = (W + kRightTW - 1) / kRightTW, ty = (H + kRightTH - 1) / kRightTH;
         const int local = t - start[i], view = local / (tx * ty), tile = local % (tx * ty);
         // view 0 is the right view; view 1 (mask off only) the left view
-        describe_right_tile<kRightPx>(reinterpret_cast<uint8_t *>(dlds),
+        describe_right_tile<kRightPx, NW % kRightRegWords == 0>(reinterpret_cast<uint8_t *>(dlds),
                                       uniform(view ? p.packedL : p.packedR), W, H, cr,
                                       uniform(view ? p.descL : p.descR),
                                       uniform((tile % tx) * kRightTW),
@@ -2259,24 +2346,35 @@ hipError_t launch_lr_check(const int32_t *dL, const int32_t *dR, int W, int H, i
 hipError_t launch_describe(const uint32_t *packed, int W, int H, const DeviceTables &t,
                            uint64_t *desc, uint64_t *mask, hipStream_t s) {
   if (!mask) {
-    static const hipError_t attr1 =
-        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<1>));
-    static const hipError_t attr4 =
-        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<kRightPx>));
-    if (attr1 != hipSuccess) return attr1;
-    if (attr4 != hipSuccess) return attr4;
+    static const hipError_t attr[4] = {
+        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<1, true>)),
+        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<1, false>)),
+        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<kRightPx, true>)),
+        allow_big_lds(reinterpret_cast<const void *>(k_describe_right<kRightPx, false>))};
+    for (hipError_t a : attr)
+      if (a != hipSuccess) return a;
     const int rows = (H + kRightTH - 1) / kRightTH;
     const int wide = (W + kRightTW - 1) / kRightTW;
     const bool four = t.tune.pair_right_px ? t.tune.pair_right_px == kRightPx
                                            : (long long)wide * rows >= kRightWideMinBlocks;
+    const RightConsts rc = right_consts(t);
     if (four) {
-      hipLaunchKernelGGL(k_describe_right<kRightPx>, dim3(wide, rows), dim3(kRightThreads),
-                         right_lds_bytes(kRightPx, t.radius, t.right_pitch), s, packed, W, H,
-                         right_consts(t), desc);
+      const size_t lds = right_lds_bytes(kRightPx, t.radius, t.right_pitch);
+      if (t.nw % kRightRegWords == 0)
+        hipLaunchKernelGGL((k_describe_right<kRightPx, true>), dim3(wide, rows),
+                           dim3(kRightThreads), lds, s, packed, W, H, rc, desc);
+      else
+        hipLaunchKernelGGL((k_describe_right<kRightPx, false>), dim3(wide, rows),
+                           dim3(kRightThreads), lds, s, packed, W, H, rc, desc);
     } else {
-      hipLaunchKernelGGL(k_describe_right<1>, dim3((W + 63) / 64, rows), dim3(kRightThreads),
-                         right_lds_bytes(1, t.radius, t.right_pitch), s, packed, W, H,
-                         right_consts(t), desc);
+      const size_t lds = right_lds_bytes(1, t.radius, t.right_pitch);
+      const dim3 grid((W + 63) / 64, rows);
+      if (t.nw % kRightGroup == 0)
+        hipLaunchKernelGGL((k_describe_right<1, true>), grid, dim3(kRightThreads), lds, s,
+                           packed, W, H, rc, desc);
+      else
+        hipLaunchKernelGGL((k_describe_right<1, false>), grid, dim3(kRightThreads), lds, s,
+                           packed, W, H, rc, desc);
     }
     return hipGetLastError();
   }
