@@ -527,7 +527,7 @@ struct DescribeConsts {
 // reads it, which keeps them out of the registers.
 template <int NW>
 __host__ __device__ constexpr int pair_table_bytes() {
-  return ((NW + 1) / 2) * 64 * 16;
+  return NW >= 32 ? (NW / 4) * 64 * 16 : ((NW + 1) / 2) * 64 * 16;
 }
 
 template <int NW>
@@ -600,6 +600,101 @@ struct RegOffsets {
   }
 };
 
+// For NW >= 32 (n >= 2048) the offsets are 16-bit halves of one dword per
+// slot, p low and q high (|offset| < 2^15 for any window and tile pitch),
+// at (j / 4) * 64 + l in dwords of four: a lane reads four slots with one
+// 16-byte load.  Wide pixels take their slots in chunks of 16 and read each
+// chunk's offsets as they go, so no group of addresses stays in registers.
+template <int NW>
+__device__ __forceinline__ void write_pair_table16(const DescribeConsts &c, uint32_t *tab) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x, n = 64 * c.nw;
+  const int32_t *pat32 = reinterpret_cast<const int32_t *>(c.pattern);
+#pragma unroll 4
+  for (int j = 0; j < NW; ++j) {
+    const int i = pair_of<NW>(lane, j);
+    const int32_t e = i < n ? pat32[i] : 0;
+    const int px = (int8_t)(e & 0xff), py = (int8_t)((e >> 8) & 0xff);
+    const int qx = (int8_t)((e >> 16) & 0xff), qy = (int8_t)((e >> 24) & 0xff);
+    const int op = 4 * (py * c.pitch + px), oq = 4 * (qy * c.pitch + qx);
+    tab[((j >> 2) * 64 + lane) * 4 + (j & 3)] =
+        (static_cast<uint32_t>(op) & 0xffffu) | (static_cast<uint32_t>(oq) << 16);
+  }
+}
+
+template <int NW>
+struct WideOffsets {
+  const uint32_t *tab;
+  // ap[j] / aq[j] = c0 + the offsets of slot 16 ch + j, j < 16
+  __device__ __forceinline__ void chunk(int c0, int lane, int ch, int *ap, int *aq) const {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint4 e = *reinterpret_cast<const uint4 *>(tab + ((4 * ch + k) * 64 + lane) * 4);
+      const uint32_t v[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ap[4 * k + i] = c0 + (static_cast<int>(v[i] << 16) >> 16);
+        aq[4 * k + i] = c0 + (static_cast<int>(v[i]) >> 16);
+      }
+    }
+  }
+};
+
+// One pixel of the descriptor and mask for NW >= 32, the slots in chunks of
+// 16: the chunk's offsets, samples, descriptor bits and packed weights, then
+// the next chunk, so that only one chunk's samples and addresses are live.
+// Chunks go from the last so that the descriptor bits shift in from slot
+// NW - 1 down to 0, as in describe_pixel.
+template <int NW>
+__device__ __forceinline__ void describe_pixel_wide(const char *lds, const WideOffsets<NW> &off,
+                                                    int centre_addr, int lane, int n, int k_eff,
+                                                    SearchHint &hint, uint64_t *out_desc,
+                                                    uint64_t *out_mask) {
+  static_assert(NW >= 32, "wide pixels have whole 32-bit descriptor registers");
+  constexpr int kChunk = 16, kRegs = NW / 32;
+  const uint32_t centre = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(
+      *reinterpret_cast<const int *>(lds + centre_addr)));
+  uint32_t d[kRegs], m[kRegs];
+#pragma unroll
+  for (int r = 0; r < kRegs; ++r) d[r] = m[r] = 0;
+  uint32_t P[NW / 2];
+#pragma unroll
+  for (int ch = NW / kChunk - 1; ch >= 0; --ch) {
+    int ap[kChunk], aq[kChunk];
+    off.chunk(centre_addr, lane, ch, ap, aq);
+    uint32_t a[kChunk], b[kChunk];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      a[j] = *reinterpret_cast<const uint32_t *>(lds + ap[j]);
+      b[j] = *reinterpret_cast<const uint32_t *>(lds + aq[j]);
+    }
+#pragma unroll
+    for (int j = kChunk - 1; j >= 0; --j) {
+      const int slot = kChunk * ch + j;
+      d[slot / 32] = __builtin_amdgcn_alignbit(d[slot / 32], (b[j] >> 24) - (a[j] >> 24), 31);
+    }
+    packed_weights<kChunk>(a, b, centre, P + (kChunk / 2) * ch);
+    // Finish the chunk here: sunk to their uses (the search, the stores),
+    // its descriptor bits and packing would keep every chunk's samples and
+    // weights live at once.
+#pragma unroll
+    for (int q = 0; q < kChunk / 2; ++q) asm volatile("" : "+v"(P[(kChunk / 2) * ch + q]));
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) asm volatile("" : "+v"(d[r]));
+  }
+  const uint32_t t1 = static_cast<uint32_t>(kth_smallest<NW / 2>(P, k_eff, 64 * NW, hint) + 1);
+#pragma unroll
+  for (int q = NW / 2 - 1; q >= 0; --q) {
+    const uint32_t x = pk_sub16(P[q], t1 | (t1 << 16));
+    m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x, 31);        // pair 2q + 1
+    m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x << 16, 31);  // pair 2q
+  }
+  if (NW * lane < n) {
+    store_lane_bits<NW>(out_desc, lane, d);
+    store_lane_bits<NW>(out_mask, lane, m);
+  }
+}
+
 // Rows of the tile go to the waves either fixed (TH / 4 consecutive rows
 // each) or, with PULL_ROWS, one at a time from the LDS counter *row_next as
 // the waves become free: a wave whose pixels needed fewer search probes then
@@ -662,18 +757,27 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
     }
     const int v = v0 + ty;
     if (v >= H) break;  // uniform
-    for (int g = 0; g < TW; g += kGroup) {
-      if (u0 + g >= W) break;  // uniform
-      const int c0 = 4 * ((ty + radius) * pitch + (g + radius));
-      int ap[NW], aq[NW];
-      off.addresses(c0, lane, ap, aq);
-#pragma unroll
-      for (int t = 0; t < kGroup; ++t) {
-        const int u = u0 + g + t;
+    if constexpr (NW >= 32) {
+      for (int g = 0; g < TW; ++g) {
+        const int u = u0 + g;
         if (u >= W) break;  // uniform
-        describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, n, k_eff, hint,
-                                   desc + ((size_t)v * W + u) * nw,
-                                   mask + ((size_t)v * W + u) * nw);
+        describe_pixel_wide<NW>(lds, off, 4 * ((ty + radius) * pitch + (g + radius)), lane, n,
+                                k_eff, hint, desc + ((size_t)v * W + u) * nw,
+                                mask + ((size_t)v * W + u) * nw);
+      }
+    } else {
+      for (int g = 0; g < TW; g += kGroup) {
+        if (u0 + g >= W) break;  // uniform
+        const int c0 = 4 * ((ty + radius) * pitch + (g + radius));
+        int ap[NW], aq[NW];
+        off.addresses(c0, lane, ap, aq);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+          const int u = u0 + g + t;
+          if (u >= W) break;  // uniform
+          describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, n, k_eff, hint,
+                             desc + ((size_t)v * W + u) * nw, mask + ((size_t)v * W + u) * nw);
+        }
       }
     }
   }
@@ -684,7 +788,12 @@ __global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
-  if constexpr (NW >= 16) {
+  if constexpr (NW >= 32) {
+    uint32_t *tab = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(tile) + c.table_off);
+    write_pair_table16<NW>(c, tab);  // the tile function's first barrier publishes it
+    describe_mask_tile<NW, TW, TH, false>(tile, nullptr, packed, W, H, c, WideOffsets<NW>{tab},
+                                          desc, mask, blockIdx.x * TW, blockIdx.y * TH);
+  } else if constexpr (NW >= 16) {
     // 4 NW offset registers would cap the kernel at four waves per SIMD
     int2 *tab = reinterpret_cast<int2 *>(reinterpret_cast<char *>(tile) + c.table_off);
     write_pair_table<NW>(c, tab);  // the tile function's first barrier publishes it
