@@ -30,10 +30,15 @@ MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix o
 
 
 def cost_on_matrix_cores(tuning, n, dmax, want_cost):
-    """Whether bsm_cost_wta takes the matrix-core kernel (the library's rule)."""
-    return (tuning.get("cost_mfma", 1) == 1 and n // 64 in (1, 2, 4, 8, 16)
-            and dmax >= tuning.get("mfma_min_dmax", 17)
-            and (not want_cost or dmax <= 256))
+    """Whether bsm_cost_wta takes a matrix-core kernel (the library's rule):
+    n <= 1024 (powers of two), or n a multiple of 1024 above it in passes of
+    512 bits without a volume, dmax <= 256 there."""
+    nw = n // 64
+    if tuning.get("cost_mfma", 1) != 1 or dmax < tuning.get("mfma_min_dmax", 17):
+        return False
+    if nw in (1, 2, 4, 8, 16):
+        return not want_cost or dmax <= 256
+    return nw > 16 and nw % 16 == 0 and not want_cost and dmax <= 256
 
 WORKLOADS = {
     0: "128x96 rectangles, dmax 16, n 256, S 15",

@@ -1602,6 +1602,131 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
 }
 
 // ===========================================================================
+// Matrix-core cost + WTA for long descriptors: nw a multiple of 16 above 16
+// (n = 2048, 3072, 4096), no volume, dmax <= 256.  The A operands of a
+// tile's 32 left pixels for all n bits would need 8 nw registers a lane, so
+// the bits go in passes of 512 (8 words): a pass builds A for its 16
+// slices, then runs every right block q over them, adding into block q's
+// accumulator, which lives across the passes (nine blocks at dmax 256:
+// 144 registers, which the compiler keeps in the accumulator registers).
+// The encoding is cost_tile_mfma's; with n up to 4096 the sums reach 16 n,
+// so the key ranks acc / 8 = n + sum v b (exact: every product is 8 v b).
+// ===========================================================================
+constexpr int kLongPassWords = 8;
+constexpr int kLongMaxBlocks = 9;  // right blocks, (dmax + 30) / 32 + 1, at dmax 256
+constexpr int kLongMaxDmax = 256;
+
+template <bool MASK>
+__device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__ descL,
+                                                    const uint64_t *__restrict__ maskL,
+                                                    const uint64_t *__restrict__ descR, int W,
+                                                    int nw, int dmax, int32_t *__restrict__ disp,
+                                                    int v, int u0) {
+  constexpr int kSlices = 2 * kLongPassWords;  // 32-bit slices of a pass
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 31, h = lane >> 5;
+  const int ua = u0 + c;
+  const bool has_a = ua < W;
+  const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * nw;
+  const uint64_t *rowR = descR + (size_t)v * W * nw;
+  const int nq = (dmax + 30) / kMfmaTX + 1;  // right blocks, <= kLongMaxBlocks
+  auto right_px = [&](int q) { return min(max(u0 - kMfmaTX * q + c, 0), W - 1); };
+  v16i32 acc[kLongMaxBlocks];
+#pragma unroll
+  for (int q = 0; q < kLongMaxBlocks; ++q)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[q][e] = 8 * 64 * nw;  // 8 (n + sum v b) >= 0
+  for (int w0 = 0; w0 < nw; w0 += kLongPassWords) {
+    // A operands of this pass (cost_tile_mfma's encoding)
+    v4i32 A[kSlices];
+    {
+      uint32_t aw[kSlices], mw[kSlices];
+      load_slices<kLongPassWords>(descL + pa_off + w0, aw);
+      if (MASK) load_slices<kLongPassWords>(maskL + pa_off + w0, mw);
+#pragma unroll
+      for (int s = 0; s < kSlices; ++s) {
+        if (!MASK) mw[s] = 0xffffffffu;
+        if (!has_a) aw[s] = mw[s] = 0;
+        const uint32_t x = aw[s] & mw[s];
+        const uint32_t py = (mw[s] & ~aw[s]) >> (4 * h), ny = x >> (4 * h);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const uint32_t pos = byte_bits(py, q4), neg = byte_bits(ny, q4);
+          A[s][q4] = static_cast<int>((pos << (3 - q4)) + (neg << 8) - (neg << (3 - q4)));
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kLongMaxBlocks; ++q) {
+      if (q < nq) {  // uniform
+        const int rb = u0 - kMfmaTX * q + c;
+        const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;
+        uint32_t bmask[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) bmask[q4] = ones << q4;
+        uint32_t bw[kSlices];
+        load_slices<kLongPassWords>(rowR + (size_t)right_px(q) * nw + w0, bw);
+#pragma unroll
+        for (int s = 0; s < kSlices; ++s) {
+          const uint32_t by = bw[s] >> (4 * h);
+          v4i32 B;
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(by & bmask[q4]);
+          acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // WTA: element e of block q is d = 32 q - c + row(e), valid when
+  // 0 <= d < dmax and the right pixel exists
+  uint32_t best[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) best[e] = 0xffffffffu;
+#pragma unroll
+  for (int q = 0; q < kLongMaxBlocks; ++q) {
+    if (q < nq) {
+      const int rb = u0 - kMfmaTX * q + c;
+      const int dbase = kMfmaTX * q - c;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
+        const uint32_t key = (static_cast<uint32_t>(acc[q][e] >> 3) << 16) | static_cast<uint32_t>(d);
+        if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      best[e] = min(best[e], static_cast<uint32_t>(__shfl_xor(static_cast<int>(best[e]), off)));
+  }
+  if (c < 16) {
+    uint32_t key = best[0];
+#pragma unroll
+    for (int e = 1; e < 16; ++e)
+      if (c == e) key = best[e];
+    const int u = u0 + 8 * (c / 4) + 4 * h + (c % 4);
+    if (u < W) disp[(size_t)v * W + u] = static_cast<int32_t>(key & 0xffffu);
+  }
+}
+
+template <bool MASK>
+__global__ __launch_bounds__(64 * kMfmaWaves) void k_cost_wta_mfma_long(
+    const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
+    const uint64_t *__restrict__ descR, int W, int H, int nw, int dmax,
+    int32_t *__restrict__ disp) {
+  // XCD-aware order, as k_cost_wta_mfma
+  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
+  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+  const int v = xcd + kXcds * (slot / groups);
+  const int tile = (slot % groups) * kMfmaWaves + (threadIdx.x >> 6);
+  if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
+  cost_tile_mfma_long<MASK>(descL, maskL, descR, W, nw, dmax, disp, v, tile * kMfmaTX);
+}
+
+// ===========================================================================
 // Cost + WTA for any n = 64 nw bits (nw outside the register-resident
 // kernel's set, up to n = 4096).  Same tiling and diagonal reuse as above
 // (one wave per row tile of 128 pixels, lane l owns a = u0 + 2l and b = a +
@@ -2511,6 +2636,19 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL, const u
       case 16: return launch_cost_mfma<16>(descL, maskL, descR, W, H, dmax, disp, cost, s);
       default: break;
     }
+  }
+  if (t.tune.cost_mfma && !cost && nw > kLongPassWords && nw % kLongPassWords == 0 &&
+      dmax >= t.tune.mfma_min_dmax && dmax <= kLongMaxDmax) {
+    const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
+    const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+    dim3 grid(kXcds * groups * ((H + kXcds - 1) / kXcds));
+    if (maskL)
+      hipLaunchKernelGGL((k_cost_wta_mfma_long<true>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
+                         maskL, descR, W, H, nw, dmax, disp);
+    else
+      hipLaunchKernelGGL((k_cost_wta_mfma_long<false>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
+                         maskL, descR, W, H, nw, dmax, disp);
+    return hipGetLastError();
   }
   switch (nw) {
     case 1: return launch_cost_fast<1>(descL, maskL, descR, W, H, dmax, disp, cost, dc, s);

@@ -184,6 +184,13 @@ MFMA_CASES = [
     (450, 2, 16, 60, True),
     (259, 3, 16, 256, True),   # largest dmax with the volume on the matrix cores, odd W
     (77, 3, 4, 40, False),     # odd W, Eq. 4
+    # long descriptors: matrix cores in passes of 512 bits (no volume,
+    # dmax <= 256), the word-chunked bitwise kernel otherwise
+    (130, 3, 32, 64, True),    # n = 2048
+    (97, 2, 48, 17, True),     # n = 3072, smallest dmax on the matrix cores
+    (259, 3, 64, 256, True),   # n = 4096, nine right blocks, odd W
+    (64, 2, 64, 33, False),    # n = 4096, Eq. 4
+    (300, 2, 32, 257, True),   # n = 2048, dmax past the long kernel
 ]
 
 
@@ -281,6 +288,15 @@ def test_match_slanted_1400x1100_radiometric(torch_cuda, bsm, orc):
     _say("case: match 1400x1100 slanted planes + radiometric change, n=1024 S=31 dmax=256")
     p = synth.CONFIG_PARAMS[2]
     _match_case(torch_cuda, bsm, orc, synth.config_scene(2), p["n"], p["S"], p["dmax"], False)
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_match_long_descriptors(torch_cuda, bsm, orc, n):
+    # the paper's n = 4096 (Section 4.1) and n = 2048: describe in chunks of
+    # 16 pairs, cost on the matrix cores in passes of 512 bits
+    _say(f"case: match 240x64 slanted planes, n={n} S=31 dmax=96")
+    sc = synth.slanted_scene(14022033, 240, 64, 96)
+    _match_case(torch_cuda, bsm, orc, sc, n, 31, 96, False)
 
 
 def test_match_without_mask(torch_cuda, bsm, orc):
