@@ -31,14 +31,14 @@ MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix o
 
 def cost_on_matrix_cores(tuning, n, dmax, want_cost):
     """Whether bsm_cost_wta takes a matrix-core kernel (the library's rule):
-    n <= 1024 (powers of two), or n a multiple of 1024 above it in passes of
+    n <= 1024 (powers of two), or n a multiple of 512 above 512 in passes of
     512 bits without a volume, dmax <= 256 there."""
     nw = n // 64
     if tuning.get("cost_mfma", 1) != 1 or dmax < tuning.get("mfma_min_dmax", 17):
         return False
     if nw in (1, 2, 4, 8, 16):
         return not want_cost or dmax <= 256
-    return nw > 16 and nw % 16 == 0 and not want_cost and dmax <= 256
+    return nw > 8 and nw % 8 == 0 and not want_cost and dmax <= 256
 
 WORKLOADS = {
     0: "128x96 rectangles, dmax 16, n 256, S 15",
@@ -48,8 +48,9 @@ WORKLOADS = {
     4: "serving: Poisson arrivals of the 64 uneven pairs, n 1024, S 31, 32 GiB admission cap",
     5: "descriptor-length sweep: 1400x1100 slanted planes + radiometric change, dmax 256, S 31, "
        "n 64..4096",
-    6: "radiometric sweep: 450x375 slanted planes, dmax 60, n 1024, S 31, right view under gain / "
-       "gamma / offset changes, BSM (Eq. 8) vs plain BRIEF (Eq. 4)",
+    6: "radiometric sweep: 450x375 slanted planes (textured; tinted; weak texture + tinted), dmax 60, "
+       "n 1024, S 31, right view under gain / gamma / offset changes, BSM (Eq. 8) vs plain BRIEF "
+       "(Eq. 4)",
 }
 
 RADIOMETRIC = [  # name, gain, gamma, per-channel offset
@@ -535,10 +536,14 @@ def bench_radiometric(args):
     dev = torch.device("cuda:0")
     rows = []
     t0 = time.perf_counter()
-    # the 450x375 scene as generated, and the same geometry with a distinct
-    # colour per surface
-    for scene_name, scene in (("textured", synth.config_scene(1)),
-                              ("tinted", synth.slanted_scene(14022021, 450, 375, 60, tinted=True))):
+    # the 450x375 scene as generated, the same geometry with a distinct
+    # colour per surface, and that again with weak, coarse texture (the
+    # surfaces' colour steps then dominate a window, where the mask matters)
+    scenes = (("textured", synth.config_scene(1)),
+              ("tinted", synth.slanted_scene(14022021, 450, 375, 60, tinted=True)),
+              ("weak texture, tinted", synth.slanted_scene(14022021, 450, 375, 60, tinted=True,
+                                                           tex_amp=12.0, tex_blur=2.0)))
+    for scene_name, scene in scenes:
         H, W = scene.left.shape[:2]
         L = torch.from_numpy(scene.left).to(dev)
         valid = synth.non_occluded(scene)

@@ -124,7 +124,8 @@ def _bilinear(t, x, y):
 
 
 def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
-                  noise=3.0, max_grad=0.2, radiometric=False, tinted=False):
+                  noise=3.0, max_grad=0.2, radiometric=False, tinted=False,
+                  tex_amp=48.0, tex_blur=1.2):
     """Slanted-plane scene: a background plane and n_regions planar patches.
 
     Patch k covers a rectangle or an ellipse (10-40 % of W and H) in left
@@ -135,7 +136,9 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
     noise; optionally the right view gets a global gain, gamma and
     per-channel offset.  With tinted=True every surface's texture gets its
     own colour offset (objects of distinct colours, as in natural scenes);
-    the default draws exactly the random numbers it always did.
+    tex_amp and tex_blur set the texture's contrast and grain (weak, coarse
+    texture leaves the surfaces' colour steps as the strongest structure in a
+    window).  The defaults draw exactly the random numbers they always did.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     Wc = W + dmax + 2
@@ -165,7 +168,7 @@ def slanted_scene(seed=14022021, W=450, H=375, dmax=60, n_regions=7,
         else:
             c = rng.uniform(min(lo_d + span, hi_d), max(hi_d - span, lo_d + span))
         planes.append(dict(kind=kind, uc=uc, vc=vc, rw=rw, rh=rh, a=a, b=b, c=c))
-    tex = [texture(rng, H, Wc) for _ in planes]
+    tex = [texture(rng, H, Wc, tex_blur, tex_amp) for _ in planes]
     if tinted:
         tint_rng = np.random.Generator(np.random.PCG64(seed + 0x7E57))
         tex = [t + tint_rng.uniform(-60.0, 60.0, 3) for t in tex]
