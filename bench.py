@@ -21,12 +21,40 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X public figures: 256 CUs x 4 SIMD16 x 2.4 GHz -> 64 32-bit integer lane
-# operations per CU per clock; HBM3E 8 TB/s.
-CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
-ALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ          # 3.93e13 lane-ops/s
+# MI355X public figures: 256 CUs at 2.4 GHz; the fp32 vector rate of 157.3
+# TFLOP/s is 128 fused multiply-adds (2 flops each) per CU and clock, i.e. 128
+# 32-bit lane operations per CU and clock; HBM3E 8 TB/s.  (Four SIMD16 units
+# alone would give 64; the vector-ALU probe of bsm_measure_peaks runs 32-bit
+# integer adds and xors at about 90 per CU and clock, above that count.)
+CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 128, 2.4e9
+ALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ          # 7.86e13 lane-ops/s
 HBM_PEAK_BPS = 8.0e12
 MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix ops/s
+
+
+def measured_peaks(args):
+    """Vector-ALU, int8 matrix and HBM rates measured on this GPU by the
+    library's probe kernels (None with --no-peaks)."""
+    if args.no_peaks:
+        return None
+    from paper_1402_2020_amd import _bsm
+    p = _bsm.bsm_measure_peaks(0, 4 << 30, 3)
+    return {"valu_int32_TOPs": round(p["valu_int32_ops"] / 1e12, 3),
+            "mfma_i8_TOPs": round(p["mfma_i8_ops"] / 1e12, 1),
+            "hbm_read_GBps": round(p["hbm_read_bps"] / 1e9, 1),
+            "hbm_copy_GBps": round(p["hbm_copy_bps"] / 1e9, 1),
+            "compute_units": p["compute_units"]}
+
+
+def with_measured_peak(roof, peaks):
+    """Adds the measured ceiling of the roofline's unit and the fraction of
+    it reached; `peak` and `frac` stay the published MI355X figures."""
+    if roof is None or peaks is None:
+        return roof
+    key = {"alu": "valu_int32_TOPs", "mfma": "mfma_i8_TOPs", "hbm": "hbm_copy_GBps"}[roof["bound"]]
+    roof["peak_measured"] = peaks[key]
+    roof["frac_of_measured"] = round(roof["achieved"] / peaks[key], 4)
+    return roof
 
 
 def cost_on_matrix_cores(tuning, n, dmax, want_cost):
@@ -140,6 +168,7 @@ def bench_batch(args):
           flush=True)
     pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, S, sigma)
     ctx = _bsm.Context(n, S, sigma, pattern=pat, device=0)
+    peaks = measured_peaks(args)
     dev = torch.device("cuda:0")
     items = [(torch.from_numpy(s.left).to(dev), torch.from_numpy(s.right).to(dev), s.dmax)
              for s in scenes]
@@ -223,6 +252,7 @@ def bench_batch(args):
     roof = {"kernel": dom, "bound": bound, "achieved": round(amount / (dms / 1e3) / scale, 3),
             "peak": round(peak / scale, 2), "unit": unit,
             "frac": round(amount / (dms / 1e3) / peak, 4), "traffic": traffic_for(dom, 3)}
+    roof = with_measured_peak(roof, peaks)
     out = {
         "metric": "disparity evals/sec (W*H*dmax/s)",
         "value": evals / (ms_batch / 1e3),
@@ -249,6 +279,7 @@ def bench_batch(args):
         "scene_generation_s": round(gen_s, 2),
         "kernels": kernels,
         "roofline": roof,
+        "measured_peaks": peaks,
     }
     # The same 64 pairs at a quarter of the size (W 80-480, H 60-270, dmax
     # 8-64): launch-bound pairs, where one persistent launch for all of them
@@ -645,6 +676,8 @@ def main():
                     help="workload (default 3: the 64 uneven pairs, the largest one-GPU "
                          "workload); 0-2 single pairs, 4 serving, 5 n-sweep, 6 radiometric")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured vector-ALU / matrix / HBM ceilings")
     ap.add_argument("--no-quarter", action="store_true",
                     help="batch workload: skip the quarter-size comparison (profiler runs, so "
                          "that every batch kernel dispatch is a full-size one)")
@@ -703,6 +736,7 @@ def main():
     pat = _bsm.bsm_make_pattern(synth.PATTERN_SEED, n, p["S"], p["sigma"])
     dev = torch.device("cuda:0")
     ctx = _bsm.Context(n, p["S"], p["sigma"], pattern=pat, device=0)
+    peaks = measured_peaks(args)
     L = torch.from_numpy(scene.left).to(dev)
     R = torch.from_numpy(scene.right).to(dev)
     disp = torch.empty((H, W), dtype=torch.int32, device=dev)
@@ -802,6 +836,8 @@ def main():
                 "peak": HBM_PEAK_BPS / 1e9, "unit": "GB/s",
                 "frac": round(achieved * 1e9 / HBM_PEAK_BPS, 4), "traffic": traffic_for(dom, cfg)}
 
+    roof = with_measured_peak(roof, peaks)
+
     # parity spot check of the timed output against a second, independent run
     # on the split entry points (both are HIP; the oracle check is in tests/)
     d1 = disp.clone()
@@ -828,6 +864,7 @@ def main():
         "wall_s_timed": round(wall, 4),
         "kernels": kernels,
         "roofline": roof,
+        "measured_peaks": peaks,
         "split_path_consistent": consistent,
     }
     if not args.no_cpu_baseline:

@@ -1,0 +1,55 @@
+/*
+ * bsm_peaks.h - measured rooflines of the GPU the library runs on.
+ *
+ * The roofline fractions of the BSM kernels are quoted against the
+ * published MI355X figures (32-bit vector lane operations: 256 CUs x 2.4 GHz
+ * x 128 per CU and clock, the rate behind the 157.3 TFLOP/s fp32 vector
+ * figure; dense int8 matrix ops 5.0 POP/s; HBM3E 8 TB/s).  This call
+ * measures what the same units reach on the device at hand, with kernels
+ * that do nothing but that work, so that a fraction can also be read
+ * against an attainable ceiling.  It is a measurement utility beside the
+ * matching calls of bsm.h and shares their status codes and
+ * bsm_last_error().
+ */
+#ifndef BSM_PEAKS_H
+#define BSM_PEAKS_H
+
+#include <stddef.h>
+
+#include "bsm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsm_peaks {
+    /* 32-bit integer vector-ALU lane operations per second: chains of
+       v_add_u32 / v_xor_b32, one lane operation per lane per instruction. */
+    double valu_int32_ops;
+    /* Dense int8 matrix operations per second: v_mfma_i32_32x32x32_i8,
+       two operations per multiply-add (32 x 32 x 32 x 2 per instruction). */
+    double mfma_i8_ops;
+    /* HBM bytes per second of a streaming read (16-byte loads) of a buffer
+       of hbm_bytes, far larger than the L2 and last-level caches. */
+    double hbm_read_bps;
+    /* HBM bytes per second of a streaming copy of hbm_bytes / 2 bytes,
+       counting the bytes read plus the bytes written. */
+    double hbm_copy_bps;
+    /* Compute units of the device (hipDeviceProp_t::multiProcessorCount). */
+    int compute_units;
+} bsm_peaks;
+
+/* Runs each probe `reps` times (>= 1) on device `device` and reports the
+   best rate of each.  hbm_bytes (a multiple of 64 KiB, at least 256 MiB)
+   is the size of the buffer the HBM probes stream; the call allocates that
+   much device memory for its duration and frees it before returning.  The
+   call synchronizes the device.  Host pointer `out` is written on success.
+   Errors: BSM_EINVAL (bad argument), BSM_ENOMEM (allocation failed),
+   BSM_EDEVICE (HIP error). */
+bsm_status bsm_measure_peaks(int device, size_t hbm_bytes, int reps, bsm_peaks *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSM_PEAKS_H */

@@ -24,6 +24,8 @@ EXPORTS = ("bsm_create", "bsm_destroy", "bsm_last_error", "bsm_make_pattern", "b
            "bsm_match_batch", "bsm_batch_stage_times", "bsm_get_tuning", "bsm_set_tuning",
            "bsm_autotune", "bsm_autotune_cached",
            "bsm_serve_config", "bsm_submit", "bsm_poll", "bsm_drain", "bsm_serve_stats")
+# Every symbol include/bsm_peaks.h declares.
+PEAK_EXPORTS = ("bsm_measure_peaks",)
 
 
 class BsmError(RuntimeError):
@@ -53,6 +55,15 @@ class ServeCounters(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
                 ("groups", C.c_uint64), ("max_in_flight_bytes", C.c_uint64),
                 ("max_group", C.c_int32), ("max_slots_busy", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Peaks(C.Structure):
+    _fields_ = [("valu_int32_ops", C.c_double), ("mfma_i8_ops", C.c_double),
+                ("hbm_read_bps", C.c_double), ("hbm_copy_bps", C.c_double),
+                ("compute_units", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -129,6 +140,7 @@ def load():
         "bsm_submit": ([vp, C.POINTER(Pair), C.POINTER(u64)], st),
         "bsm_poll": ([vp, u64, C.POINTER(i32), C.POINTER(Times)], st),
         "bsm_drain": ([vp], st),
+        "bsm_measure_peaks": ([i32, sz, i32, C.POINTER(Peaks)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -293,6 +305,13 @@ def bsm_drain(ctx):
 
 
 # ---- convenience layer over torch tensors --------------------------------
+
+def bsm_measure_peaks(device=0, hbm_bytes=4 << 30, reps=3):
+    """Measured vector-ALU, int8 matrix and HBM rates of the device (dict)."""
+    out = Peaks()
+    _check(load().bsm_measure_peaks(device, hbm_bytes, reps, C.byref(out)), "bsm_measure_peaks")
+    return out.as_dict()
+
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())

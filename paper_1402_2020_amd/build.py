@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("BSM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["bsm_host.cpp", "bsm_kernels.hip", "bsm_batch.cpp", "bsm_serve_core.cpp", "bsm_server.cpp",
-           "bsm_noalloc.hip"]
+           "bsm_noalloc.hip", "bsm_peaks.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-result",
           "-I", os.path.join(HERE, "..", "include")]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

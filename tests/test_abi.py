@@ -17,6 +17,7 @@ from paper_1402_2020_amd import _bsm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "bsm.h")
+PEAKS_HEADER = os.path.join(ROOT, "include", "bsm_peaks.h")
 
 
 @pytest.fixture(scope="module")
@@ -24,27 +25,30 @@ def lib():
     return _bsm.load()
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(bsm_[a-z_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
     assert _declared_functions() == sorted(_bsm.EXPORTS)
+    assert _declared_functions(PEAKS_HEADER) == sorted(_bsm.PEAK_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol(lib):
-    for name in _declared_functions():
+    declared = _declared_functions() + _declared_functions(PEAKS_HEADER)
+    for name in declared:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", _bsm.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r" T (bsm_[a-z_]+)$", out, flags=re.M))
-    assert set(_declared_functions()) <= exported
+    assert set(declared) <= exported
 
 
 STRUCTS = (("bsm_params", "Params"), ("bsm_pair", "Pair"), ("bsm_times", "Times"),
-           ("bsm_tuning", "Tuning"), ("bsm_serve_counters", "ServeCounters"))
+           ("bsm_tuning", "Tuning"), ("bsm_serve_counters", "ServeCounters"),
+           ("bsm_peaks", "Peaks"))
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -55,7 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
         for fname, _ in getattr(_bsm, cname)._fields_:
             lines.append(f'  printf("{T}.{fname} %zu\\n", offsetof({T}, {fname}));')
     src = tmp_path / "layout.c"
-    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"bsm.h\"\n"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"bsm_peaks.h\"\n"
                    "int main(void) {\n" + "\n".join(lines) + "\n  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
@@ -118,3 +122,12 @@ def test_null_context_is_rejected(lib):
     assert lib.bsm_cost_wta(None, None, None, None, 4, 4, 1, None, None, None) == _bsm.EINVAL
     assert lib.bsm_footprint(None, 4, 4, 1, 0) == 0
     lib.bsm_destroy(None)
+
+
+@pytest.mark.parametrize("hbm_bytes,reps,null_out", [(4 << 30, 0, False), (1 << 20, 3, False),
+                                                     ((256 << 20) + 4096, 3, False),
+                                                     (4 << 30, 3, True)])
+def test_measure_peaks_rejects_bad_arguments_before_device(lib, hbm_bytes, reps, null_out):
+    out = None if null_out else C.byref(_bsm.Peaks())
+    assert lib.bsm_measure_peaks(0, hbm_bytes, reps, out) == _bsm.EINVAL
+    assert _bsm.bsm_last_error()
