@@ -137,11 +137,11 @@ __global__ __launch_bounds__(256) void k_lr_check(const int32_t *__restrict__ dL
 //            wave's tests IS word j, moved into lane j with v_writelane.
 // ===========================================================================
 // Tile height (rows) of the describe+mask tiles: eight rows when the image
-// has tiles enough to fill the GPU several times over (fewer halo rows per
-// output row), four rows otherwise (twice the tiles, shorter tails).  The
+// has tiles enough to fill the GPU about once (fewer halo rows per output
+// row), four rows otherwise (twice the tiles, shorter tails).  The
 // persistent batch kernel takes the height its tuning names (8 or 16 rows).
 constexpr int kDescTH = 8, kDescTHSmall = 4, kDescThreads = 256;
-constexpr long long kDescTallMinTiles = 4096;  // four rounds of the GPU at four blocks per CU
+constexpr long long kDescTallMinTiles = 1024;  // one round of the GPU at four blocks per CU
 
 // Pair index of slot j of lane `lane` (0-based).
 template <int NW>
@@ -426,6 +426,36 @@ __device__ __forceinline__ void packed_weights(const uint32_t *a, const uint32_t
   if constexpr (NW & 1) P[NW / 2] = pack_halves(w[NW - 1], 0x7fffu);
 }
 
+// The lane's mask bits (Eq. 6-7) for NW >= 8 pairs packed two per dword in
+// P: bit j of m[j / 32] is [w_j <= T], t1 = T + 1.  Eight pairs at a time:
+// the signs of their halves of P - t1 become bytes of 0x00 / 0xff
+// (v_perm_b32 sign selectors, four pairs per dword), a mask keeps 2^i in
+// the byte of pair i of the eight, and v_sad_u8 adds the bytes up on top of
+// the register's higher groups shifted up by eight bits.
+template <int NW>
+__device__ __forceinline__ void mask_bits(const uint32_t *P, uint32_t t1, uint32_t *m) {
+  static_assert(NW % 8 == 0, "whole groups of eight pairs");
+  const uint32_t t1x2 = t1 | (t1 << 16);
+  constexpr int kRegs = (NW + 31) / 32;
+#pragma unroll
+  for (int r = 0; r < kRegs; ++r) {
+    constexpr int kGroups = NW / 8 < 4 ? NW / 8 : 4;  // groups of eight in a register
+    uint32_t acc = 0;
+#pragma unroll
+    for (int g = kGroups - 1; g >= 0; --g) {
+      const int q = 16 * r + 4 * g;  // dwords q .. q + 3 hold pairs 2q .. 2q + 7
+      // bytes 0-3: signs of P[q].lo, P[q].hi, P[q + 1].lo, P[q + 1].hi
+      const uint32_t lo = __builtin_amdgcn_perm(pk_sub16(P[q + 1], t1x2), pk_sub16(P[q], t1x2),
+                                                0x0b0a0908u) & 0x08040201u;
+      const uint32_t hi = __builtin_amdgcn_perm(pk_sub16(P[q + 3], t1x2),
+                                                pk_sub16(P[q + 2], t1x2), 0x0b0a0908u) &
+                          0x80402010u;
+      acc = __builtin_amdgcn_sad_u8(hi, 0u, __builtin_amdgcn_sad_u8(lo, 0u, acc << 8));
+    }
+    m[r] = acc;
+  }
+}
+
 // Stores a lane's NW consecutive bits (NW >= 8) at byte NW / 8 * lane of
 // the pixel's words.
 template <int NW>
@@ -480,13 +510,7 @@ __device__ __forceinline__ void describe_pixel(const char *lds, const int *ap, c
     uint32_t P[NW / 2];
     packed_weights<NW>(a, b, centre, P);
     const uint32_t t1 = static_cast<uint32_t>(kth_smallest<NW / 2>(P, k_eff, 64 * NW, hint) + 1);
-    // halves of P - (T + 1): negative exactly for the pairs with w <= T
-#pragma unroll
-    for (int q = NW / 2 - 1; q >= 0; --q) {
-      const uint32_t x = pk_sub16(P[q], t1 | (t1 << 16));
-      m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x, 31);        // pair 2q + 1
-      m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x << 16, 31);  // pair 2q
-    }
+    mask_bits<NW>(P, t1, m);
     if (NW * lane < n) {
       store_lane_bits<NW>(out_desc, lane, d);
       store_lane_bits<NW>(out_mask, lane, m);
@@ -683,12 +707,7 @@ __device__ __forceinline__ void describe_pixel_wide(const char *lds, const WideO
     for (int r = 0; r < kRegs; ++r) asm volatile("" : "+v"(d[r]));
   }
   const uint32_t t1 = static_cast<uint32_t>(kth_smallest<NW / 2>(P, k_eff, 64 * NW, hint) + 1);
-#pragma unroll
-  for (int q = NW / 2 - 1; q >= 0; --q) {
-    const uint32_t x = pk_sub16(P[q], t1 | (t1 << 16));
-    m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x, 31);        // pair 2q + 1
-    m[q / 16] = __builtin_amdgcn_alignbit(m[q / 16], x << 16, 31);  // pair 2q
-  }
+  mask_bits<NW>(P, t1, m);
   if (NW * lane < n) {
     store_lane_bits<NW>(out_desc, lane, d);
     store_lane_bits<NW>(out_mask, lane, m);
