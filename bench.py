@@ -21,13 +21,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X public figures: 256 CUs at 2.4 GHz; the fp32 vector rate of 157.3
-# TFLOP/s is 128 fused multiply-adds (2 flops each) per CU and clock, i.e. 128
-# 32-bit lane operations per CU and clock; HBM3E 8 TB/s.  (Four SIMD16 units
-# alone would give 64; the vector-ALU probe of bsm_measure_peaks runs 32-bit
-# integer adds and xors at about 90 per CU and clock, above that count.)
-CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 128, 2.4e9
-ALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ          # 7.86e13 lane-ops/s
+# MI355X public figures: 256 CUs x 4 SIMD16 at 2.4 GHz -> 64 unpacked 32-bit
+# lane operations per CU and clock (the fp64 vector rate, 78.6 TFLOP/s, is
+# that many FMAs; fp32's 157.3 counts packed pairs); HBM3E 8 TB/s.  Plain
+# adds and xors issue faster on gfx950 (bsm_measure_peaks' valu_addxor_ops).
+CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
+ALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ          # 3.93e13 lane-ops/s
 HBM_PEAK_BPS = 8.0e12
 MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix ops/s
 
@@ -40,6 +39,7 @@ def measured_peaks(args):
     from paper_1402_2020_amd import _bsm
     p = _bsm.bsm_measure_peaks(0, 4 << 30, 3)
     return {"valu_int32_TOPs": round(p["valu_int32_ops"] / 1e12, 3),
+            "valu_addxor_TOPs": round(p["valu_addxor_ops"] / 1e12, 3),
             "mfma_i8_TOPs": round(p["mfma_i8_ops"] / 1e12, 1),
             "hbm_read_GBps": round(p["hbm_read_bps"] / 1e9, 1),
             "hbm_copy_GBps": round(p["hbm_copy_bps"] / 1e9, 1),

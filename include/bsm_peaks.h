@@ -3,8 +3,8 @@
  *
  * The roofline fractions of the BSM kernels are quoted against the
  * published MI355X figures (32-bit vector lane operations: 256 CUs x 2.4 GHz
- * x 128 per CU and clock, the rate behind the 157.3 TFLOP/s fp32 vector
- * figure; dense int8 matrix ops 5.0 POP/s; HBM3E 8 TB/s).  This call
+ * x 64 per CU and clock, the unpacked rate behind the 78.6 TFLOP/s fp64
+ * vector figure; dense int8 matrix ops 5.0 POP/s; HBM3E 8 TB/s).  This call
  * measures what the same units reach on the device at hand, with kernels
  * that do nothing but that work, so that a fraction can also be read
  * against an attainable ceiling.  It is a measurement utility beside the
@@ -23,9 +23,13 @@ extern "C" {
 #endif
 
 typedef struct bsm_peaks {
-    /* 32-bit integer vector-ALU lane operations per second: chains of
-       v_add_u32 / v_xor_b32, one lane operation per lane per instruction. */
+    /* 32-bit integer vector-ALU lane operations per second (one per lane
+       per instruction) of the kinds the describe and cost kernels issue
+       most: v_perm_b32, v_bcnt_u32_b32, v_alignbit_b32, v_pk_sub_u16,
+       v_msad_u8, v_max_u32, v_and_or_b32, v_bitop3_b32, in equal shares. */
     double valu_int32_ops;
+    /* The same for plain v_add_u32 / v_xor_b32, which issue faster. */
+    double valu_addxor_ops;
     /* Dense int8 matrix operations per second: v_mfma_i32_32x32x32_i8,
        two operations per multiply-add (32 x 32 x 32 x 2 per instruction). */
     double mfma_i8_ops;

@@ -20,25 +20,47 @@ constexpr int kMfmaIters = 2048;
 constexpr int kMfmaChains = 4;     // independent accumulators per wave
 constexpr double kMfmaOps = 32.0 * 32.0 * 32.0 * 2.0;
 
-// Four independent chains of alternating adds and xors, 32 instructions per
-// iteration written out in assembly so that none is folded or removed.
+// Four independent chains, 32 instructions per iteration written out in
+// assembly so that none is folded or removed.  MIX: the kinds the describe
+// and cost kernels issue most (byte permute, bit count, funnel shift, packed
+// 16-bit subtract, masked byte SAD, max, and-or, three-input bit operation);
+// otherwise alternating adds and xors, which issue faster on gfx950.
+#define BSM_PEAK_ADDXOR(j) "v_add_u32 %" #j ", %" #j ", %4\n\tv_xor_b32 %" #j ", %" #j ", %4\n\t"
+#define BSM_PEAK_MIX_A(j) \
+  "v_perm_b32 %" #j ", %" #j ", %4, %5\n\tv_bcnt_u32_b32 %" #j ", %" #j ", %4\n\t"
+#define BSM_PEAK_MIX_B(j) \
+  "v_alignbit_b32 %" #j ", %" #j ", %4, 31\n\tv_pk_sub_u16 %" #j ", %" #j ", %4\n\t"
+#define BSM_PEAK_MIX_C(j) \
+  "v_msad_u8 %" #j ", %" #j ", %4, %" #j "\n\tv_max_u32 %" #j ", %" #j ", %4\n\t"
+#define BSM_PEAK_MIX_D(j) \
+  "v_and_or_b32 %" #j ", %" #j ", %4, %5\n\tv_bitop3_b32 %" #j ", %" #j ", %4, %5 bitop3:0x1e\n\t"
+#define BSM_PEAK_ALL(M) M(0) M(1) M(2) M(3)
+template <bool MIX>
 __global__ __launch_bounds__(kThreads) void k_peak_valu(uint32_t seed, int iters,
                                                         uint32_t *__restrict__ out) {
   const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
   uint32_t a = seed ^ gid, b = a * 3u + 1u, c = a * 5u + 7u, d = a * 9u + 3u;
-  const uint32_t k = seed | 1u;
+  const uint32_t k = seed | 1u, k2 = seed ^ 0x0c0c0404u;
   for (int i = 0; i < iters; ++i) {
-#define BSM_PEAK_ROUND                                                                    \
-  "v_add_u32 %0, %0, %4\n\tv_add_u32 %1, %1, %4\n\tv_add_u32 %2, %2, %4\n\tv_add_u32 %3, %3, " \
-  "%4\n\tv_xor_b32 %0, %0, %4\n\tv_xor_b32 %1, %1, %4\n\tv_xor_b32 %2, %2, %4\n\tv_xor_b32 "   \
-  "%3, %3, %4\n\t"
-    asm volatile(BSM_PEAK_ROUND BSM_PEAK_ROUND BSM_PEAK_ROUND BSM_PEAK_ROUND
-                 : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
-                 : "v"(k));
-#undef BSM_PEAK_ROUND
+    if constexpr (MIX)
+      asm volatile(BSM_PEAK_ALL(BSM_PEAK_MIX_A) BSM_PEAK_ALL(BSM_PEAK_MIX_B)
+                       BSM_PEAK_ALL(BSM_PEAK_MIX_C) BSM_PEAK_ALL(BSM_PEAK_MIX_D)
+                   : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+                   : "v"(k), "v"(k2));
+    else
+      asm volatile(BSM_PEAK_ALL(BSM_PEAK_ADDXOR) BSM_PEAK_ALL(BSM_PEAK_ADDXOR)
+                       BSM_PEAK_ALL(BSM_PEAK_ADDXOR) BSM_PEAK_ALL(BSM_PEAK_ADDXOR)
+                   : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+                   : "v"(k), "v"(k2));
   }
   out[gid] = a ^ b ^ c ^ d;
 }
+#undef BSM_PEAK_ALL
+#undef BSM_PEAK_MIX_D
+#undef BSM_PEAK_MIX_C
+#undef BSM_PEAK_MIX_B
+#undef BSM_PEAK_MIX_A
+#undef BSM_PEAK_ADDXOR
 
 __global__ __launch_bounds__(kThreads) void k_peak_mfma(int seed, int iters,
                                                         int *__restrict__ out) {
@@ -166,11 +188,15 @@ extern "C" bsm_status bsm_measure_peaks(int device, size_t hbm_bytes, int reps, 
   const size_t n16 = hbm_bytes / 16, half16 = n16 / 2;
   const uint4 *src = static_cast<const uint4 *>(p.buf);
   uint4 *dst = static_cast<uint4 *>(p.buf) + half16;
-  float t_valu, t_mfma, t_read, t_copy;
+  float t_valu, t_addxor, t_mfma, t_read, t_copy;
   if ((e = best_ms([&] {
-         hipLaunchKernelGGL(k_peak_valu, dim3(valu_blocks), dim3(kThreads), 0, p.s, 0x9e3779b9u,
-                            kValuIters, static_cast<uint32_t *>(p.out));
+         hipLaunchKernelGGL(k_peak_valu<true>, dim3(valu_blocks), dim3(kThreads), 0, p.s,
+                            0x9e3779b9u, kValuIters, static_cast<uint32_t *>(p.out));
        }, &t_valu)) != hipSuccess ||
+      (e = best_ms([&] {
+         hipLaunchKernelGGL(k_peak_valu<false>, dim3(valu_blocks), dim3(kThreads), 0, p.s,
+                            0x9e3779b9u, kValuIters, static_cast<uint32_t *>(p.out));
+       }, &t_addxor)) != hipSuccess ||
       (e = best_ms([&] {
          hipLaunchKernelGGL(k_peak_mfma, dim3(mfma_blocks), dim3(kThreads), 0, p.s, 0x1402,
                             kMfmaIters, static_cast<int *>(p.out));
@@ -188,6 +214,7 @@ extern "C" bsm_status bsm_measure_peaks(int device, size_t hbm_bytes, int reps, 
   const double valu_lane_ops = (double)valu_blocks * kThreads * kValuIters * kValuPerIter;
   const double mfma_ops = (double)mfma_blocks * (kThreads / 64) * kMfmaIters * kMfmaChains * kMfmaOps;
   out->valu_int32_ops = valu_lane_ops / (t_valu * 1e-3);
+  out->valu_addxor_ops = valu_lane_ops / (t_addxor * 1e-3);
   out->mfma_i8_ops = mfma_ops / (t_mfma * 1e-3);
   out->hbm_read_bps = (double)n16 * 16 / (t_read * 1e-3);
   out->hbm_copy_bps = (double)half16 * 16 * 2 / (t_copy * 1e-3);

@@ -15,9 +15,12 @@ def torch_cuda():
     return torch
 
 PUBLISHED = {
-    # 256 CUs x 2.4 GHz x 128 lane operations per CU and clock (the rate
-    # behind the published 157.3 TFLOP/s fp32 vector figure)
-    "valu_int32_ops": 256 * 128 * 2.4e9,
+    # 256 CUs x 2.4 GHz x 64 lanes: one unpacked lane operation per lane
+    # and clock (the rate behind the 78.6 TFLOP/s fp64 vector figure)
+    "valu_int32_ops": 256 * 64 * 2.4e9,
+    # adds and xors issue faster, at most at the packed rate behind the
+    # 157.3 TFLOP/s fp32 vector figure (128 per CU and clock)
+    "valu_addxor_ops": 256 * 128 * 2.4e9,
     # dense int8 matrix operations per second
     "mfma_i8_ops": 5.0e15,
     # HBM3E
