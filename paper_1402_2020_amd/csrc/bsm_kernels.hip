@@ -914,7 +914,9 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
                                                     uint64_t *__restrict__ desc, int u0, int v0) {
   constexpr int TW = 64 * PX;
   uint64_t *stage_all = reinterpret_cast<uint64_t *>(lds);
-  uint8_t *itile = lds + right_stage_bytes(PX);
+  // The register path stages nothing, so its tile starts at the bottom of
+  // LDS, and a sample's address is one add from the lane's base.
+  uint8_t *itile = lds + (kWhole && PX == 4 ? 0 : right_stage_bytes(PX));
   const int radius = c.radius, pitch = c.pitch, nw = c.nw;
   const int hx = right_halo(radius);  // tile column of pixel u0
   const int rows = kRightTH + 2 * radius, cols = hx + TW + radius;
@@ -1029,27 +1031,55 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
       // registers, then each pixel's 64 bytes as four 16-byte stores in a
       // row: the half-lines are complete when they leave, so no partly
       // written line waits in the cache for the rest of the pixel's string.
+      //
+      // The four pixels' tests of one pair are one byte-parallel compare:
+      // byte k of P and Q holds I(p), I(q) of pixel k, and the top bit of
+      // byte k of lt is [I(q) < I(p)] (the compare of the low seven bits
+      // in the top bit of (Q | 0x80) - (P & 0x7f), which borrows across no
+      // byte, then the top bits decide).  Eight pairs shift into byte k of
+      // e from the top, so e holds eight bits of each pixel; four such
+      // registers are transposed into the pixels' 32-bit halves.
       const uint8_t *lp = itile + base;  // the lane's first pixel, 4-byte aligned
       uint64_t *out = desc + ((size_t)v * W + px0) * nw;
+      static_assert(PX == 4, "byte-parallel tests of four pixels");
+      constexpr uint32_t kTop = 0x80808080u;
       for (int g0 = 0; g0 < nw; g0 += kRightRegWords) {
         uint32_t words[kRightRegWords][2][PX];
         for_words<kRightRegWords>([&](auto J) {
           constexpr int jj = J.value;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            uint32_t acc[PX] = {};
-#pragma unroll 8
-            for (int b = 31; b >= 0; --b) {
-              const int2 o = offs[64 * (g0 + jj) + 32 * h + b];  // uniform: scalar load
-              const uint32_t P = lane_bytes4(lp, o.x), Q = lane_bytes4(lp, o.y);
+            // e[3 - r] after the loop: pairs 8r .. 8r + 7 (a rolled loop
+            // keeps the offsets of one group of eight in scalar registers)
+            uint32_t e[4] = {0, 0, 0, 0};
+#pragma unroll 1
+            for (int r = 0; r < 4; ++r) {
+              uint32_t x = 0;
 #pragma unroll
-              for (int k = 0; k < PX; ++k) {
-                const uint32_t diff = ((Q >> (8 * k)) & 0xffu) - ((P >> (8 * k)) & 0xffu);
-                acc[k] = __builtin_amdgcn_alignbit(acc[k], diff, 31);
+              for (int b = 8 * r; b < 8 * r + 8; ++b) {
+                const int2 o = offs[64 * (g0 + jj) + 32 * h + b];  // uniform: scalar load
+                const uint32_t P = lane_bytes4(lp, o.x), Q = lane_bytes4(lp, o.y);
+                const uint32_t low = (Q | kTop) - (P & ~kTop);
+                // top bits: (!q7 & p7) | (!(q7 ^ p7) & !low7), as one
+                // three-input bit operation (truth table on Q = 0xf0,
+                // P = 0xcc, low = 0xaa)
+                const uint32_t lt = __builtin_amdgcn_bitop3_b32(Q, P, low, 0x4d);
+                x = (lt & kTop) | ((x >> 1) & ~kTop);
               }
+              e[3] = e[2];
+              e[2] = e[1];
+              e[1] = e[0];
+              e[0] = x;
             }
-#pragma unroll
-            for (int k = 0; k < PX; ++k) words[jj][h][k] = acc[k];
+            // halves of pixels 0-3: bytes k of e[3], e[2], e[1], e[0]
+            const uint32_t t01 = __builtin_amdgcn_perm(e[2], e[3], 0x05010400u);
+            const uint32_t t23 = __builtin_amdgcn_perm(e[0], e[1], 0x05010400u);
+            const uint32_t u01 = __builtin_amdgcn_perm(e[2], e[3], 0x07030602u);
+            const uint32_t u23 = __builtin_amdgcn_perm(e[0], e[1], 0x07030602u);
+            words[jj][h][0] = __builtin_amdgcn_perm(t23, t01, 0x05040100u);
+            words[jj][h][1] = __builtin_amdgcn_perm(t23, t01, 0x07060302u);
+            words[jj][h][2] = __builtin_amdgcn_perm(u23, u01, 0x05040100u);
+            words[jj][h][3] = __builtin_amdgcn_perm(u23, u01, 0x07060302u);
           }
         });
 #pragma unroll
