@@ -1464,9 +1464,30 @@ __device__ __forceinline__ void load_slices(const uint64_t *p, uint32_t *out) {
   }
 }
 
-// Bits q, q + 8, q + 16, q + 24 of y as the four bytes of a dword (0 or 1).
-__device__ __forceinline__ uint32_t byte_bits(uint32_t y, int q) {
-  return (y >> q) & 0x01010101u;
+// The four A dwords of one 32-bit slice for lane half h: byte r of dword q
+// is v w for bit 8r + 4h + q, with v = +1 for (m, !a), -1 for (m, a), 0 for
+// !m, and w = 8 >> q (the B byte of the same bit holds 2^q, so every
+// product is 8 v b).  Nibble h of p = m & !a and of n = m & a are
+// interleaved per byte (n3 p3 n2 p2 n1 p1 n0 p0), so that bits 2q, 2q + 1
+// form a v_perm_b32 selector 2 n + p into the bytes (0, w, -w) of a
+// constant.  v_bitop3_b32 immediates are truth tables over the operands
+// 0xf0, 0xcc, 0xaa: 0x20 = x & !y & z, 0x80 = x & y & z, 0xca = x ? y : z.
+__device__ __forceinline__ void a_operands(uint32_t aw, uint32_t mw, int h, v4i32 &A) {
+  const uint32_t as = aw >> (4 * h), ms = mw >> (4 * h);
+  const uint32_t p = __builtin_amdgcn_bitop3_b32(ms, as, 0x0f0f0f0fu, 0x20);
+  const uint32_t n = __builtin_amdgcn_bitop3_b32(ms, as, 0x0f0f0f0fu, 0x80);
+  const uint32_t x0 = (n << 4) | p;  // n3 n2 n1 n0 p3 p2 p1 p0
+  // swap bit pairs 5:4 and 3:2, then bits 6 and 5, 2 and 1
+  const uint32_t x1 = __builtin_amdgcn_bitop3_b32(
+      0x30303030u, x0 << 2, __builtin_amdgcn_bitop3_b32(0x0c0c0c0cu, x0 >> 2, x0, 0xca), 0xca);
+  const uint32_t x2 = __builtin_amdgcn_bitop3_b32(
+      0x44444444u, x1 << 1, __builtin_amdgcn_bitop3_b32(0x22222222u, x1 >> 1, x1, 0xca), 0xca);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    constexpr uint32_t kW[4] = {8, 4, 2, 1};
+    const uint32_t table = ((256u - kW[q]) << 16) | (kW[q] << 8);  // bytes 0, w, -w, 0
+    A[q] = static_cast<int>(__builtin_amdgcn_perm(table, table, (x2 >> (2 * q)) & 0x03030303u));
+  }
 }
 
 // Largest dmax of the matrix-core kernel with a volume: the wave's slab of
@@ -1504,17 +1525,8 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
     for (int s = 0; s < kSlices; ++s) {
       if (!MASK) mw[s] = 0xffffffffu;
       if (!has_a) aw[s] = mw[s] = 0;
-      const uint32_t x = aw[s] & mw[s];
-      if (VOL) am += __builtin_popcount(x);
-      // bytes +w for (m, !a), -w for (m, a), 0 for !m, w = 8 >> q: the B
-      // byte of the same bit holds 2^q (see below), so every product is 8 v b.
-      // As integers, pos << k + neg (256 - w) with k = 3 - q; no byte carries.
-      const uint32_t py = (mw[s] & ~aw[s]) >> (4 * h), ny = x >> (4 * h);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t pos = byte_bits(py, q), neg = byte_bits(ny, q);
-        A[s][q] = static_cast<int>((pos << (3 - q)) + (neg << 8) - (neg << (3 - q)));
-      }
+      if (VOL) am += __builtin_popcount(aw[s] & mw[s]);
+      a_operands(aw[s], mw[s], h, A[s]);
     }
   }
   // costs: C = popcount(a & m) + sum v b = am_row + acc / 8 - n
@@ -1696,13 +1708,7 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
       for (int s = 0; s < kSlices; ++s) {
         if (!MASK) mw[s] = 0xffffffffu;
         if (!has_a) aw[s] = mw[s] = 0;
-        const uint32_t x = aw[s] & mw[s];
-        const uint32_t py = (mw[s] & ~aw[s]) >> (4 * h), ny = x >> (4 * h);
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const uint32_t pos = byte_bits(py, q4), neg = byte_bits(ny, q4);
-          A[s][q4] = static_cast<int>((pos << (3 - q4)) + (neg << 8) - (neg << (3 - q4)));
-        }
+        a_operands(aw[s], mw[s], h, A[s]);
       }
     }
 #pragma unroll
