@@ -1545,6 +1545,14 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
   uint32_t bw[kSlices];
   load_slices<NW>(rowR + (size_t)right_px(0) * NW, bw);
   for (int q = 0; q < nq; ++q) {
+    // The next block's words load into bw as this block's products use
+    // them up (16 bytes per four slices), so that they have the whole block
+    // to arrive.  The loads are unconditional (after the last block they
+    // read a clamped pixel of the row again) and through global pointers,
+    // so that each wait covers exactly the load it needs.
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) u32x4 *GlobalU4;
+    const GlobalU4 next = (GlobalU4)(rowR + (size_t)right_px(q + 1) * NW);
     const int rb = u0 - kMfmaTX * q + c;  // the lane's right pixel
     // B dword q4 keeps bits q4 + 8r of the shifted word in place (byte
     // value 2^q4), one AND each; a missing right pixel gives B = 0.
@@ -1562,9 +1570,25 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(by & bmask[q4]);
       acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc, 0, 0, 0);
+      if constexpr (NW % 2 == 0) {
+        if ((s & 3) == 3) {
+          const u32x4 x = next[s / 4];
+          bw[s - 3] = x[0];
+          bw[s - 2] = x[1];
+          bw[s - 1] = x[2];
+          bw[s] = x[3];
+          // keep the load here: scheduled freely, all of them sink to the
+          // end of the block and arrive late
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else if (s == kSlices - 1) {  // NW = 1: one 8-byte word
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        typedef const __attribute__((address_space(1))) u32x2 *GlobalU2;
+        const u32x2 x = *(GlobalU2)(rowR + (size_t)right_px(q + 1));
+        bw[0] = x[0];
+        bw[1] = x[1];
+      }
     }
-    // the next block's words load while this block's products finish
-    if (q + 1 < nq) load_slices<NW>(rowR + (size_t)right_px(q + 1) * NW, bw);
     // d of element e is dbase + row(e); valid when 0 <= d < dmax and the
     // right pixel exists (u - d = rb >= 0).  Blocks whose every entry is
     // valid (the wave-uniform test below) skip the per-element checks.

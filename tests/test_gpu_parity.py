@@ -106,6 +106,24 @@ def test_describe_parity(torch_cuda, bsm, orc, W, H, n, S, k):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [64, 192, 512, 1536, 2048, 4096])
+def test_describe_right_four_pixels_per_lane(torch_cuda, bsm, orc, n):
+    # the other view's descriptor with four pixels per lane forced: the
+    # byte-parallel register path (n a multiple of 512) and the staged path
+    # (other n), on a width that leaves a ragged last tile (301 = 256 + 45)
+    torch = torch_cuda
+    _say(f"case: describe right view, four pixels per lane, n={n}")
+    ctx, pat = _ctx(bsm, orc, n, 31)
+    tune = ctx.tuning()
+    tune["pair_right_px"] = 4
+    ctx.set_tuning(tune)
+    img = np.ascontiguousarray(synth.slanted_scene(1402 + n, 301, 19, 6).left)
+    desc, _ = ctx.describe(_dev(torch, img), with_mask=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u64(desc), orc.describe(img, pat))
+    ctx.close()
+
+
 def test_describe_flat_and_random(torch_cuda, bsm, orc):
     torch = torch_cuda
     _say("case: describe flat + uniform random")
