@@ -20,6 +20,24 @@ namespace {
 
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
+// A wave-uniform value pinned to scalar registers.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename T>
+__device__ __forceinline__ T *uniform(T *p) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
+  const uint32_t hi =
+      static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x >> 32)));
+  return reinterpret_cast<T *>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// The wave's index in its workgroup, marked wave-uniform: derived from
+// threadIdx.x, it would otherwise make every row and address computed from
+// it per-lane vector arithmetic (64-bit multiplies included).
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
 // ===========================================================================
 // Colour pre-pass.  Output uint32 per pixel: byte 0 L8, byte 1 a8, byte 2 b8,
 // byte 3 intensity I.  Tiles of 64 x (4 RPT) pixels, RPT rows per thread:
@@ -754,7 +772,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
       }
     }
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int k_eff = c.k + (64 * NW - n);
   if (PULL_ROWS && threadIdx.x == 0) *row_next = 0;
   __syncthreads();
@@ -776,13 +794,15 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
     }
     const int v = v0 + ty;
     if (v >= H) break;  // uniform
+    // the row's first word, from scalar registers (v W < 2^31)
+    const size_t row_words = static_cast<size_t>(uniform(v * W)) * static_cast<size_t>(nw);
     if constexpr (NW >= 32) {
       for (int g = 0; g < TW; ++g) {
         const int u = u0 + g;
         if (u >= W) break;  // uniform
         describe_pixel_wide<NW>(lds, off, 4 * ((ty + radius) * pitch + (g + radius)), lane, n,
-                                k_eff, hint, desc + ((size_t)v * W + u) * nw,
-                                mask + ((size_t)v * W + u) * nw);
+                                k_eff, hint, uniform(desc + row_words + uniform(u * nw)),
+                                uniform(mask + row_words + uniform(u * nw)));
       }
     } else {
       for (int g = 0; g < TW; g += kGroup) {
@@ -794,8 +814,11 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
         for (int t = 0; t < kGroup; ++t) {
           const int u = u0 + g + t;
           if (u >= W) break;  // uniform
+          // the words' addresses on the scalar unit (used only under the
+          // lanes' store condition, they would be computed per lane there)
           describe_pixel<NW>(lds, ap, aq, c0 + 4 * t, 4 * t, lane, n, k_eff, hint,
-                             desc + ((size_t)v * W + u) * nw, mask + ((size_t)v * W + u) * nw);
+                             uniform(desc + row_words + uniform(u * nw)),
+                             uniform(mask + row_words + uniform(u * nw)));
         }
       }
     }
@@ -946,7 +969,7 @@ __device__ __forceinline__ void describe_right_tile(uint8_t *lds,
     }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int ty = wave, v = v0 + ty;  // one row per wave
   if (v >= H) return;                // no barrier follows in this tile
   const int base = (ty + radius) * pitch + hx + PX * lane;  // multiple of 4 for PX = 4
@@ -1662,7 +1685,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
   const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int v = xcd + kXcds * (slot / groups);
-  const int tile = (slot % groups) * kMfmaWaves + (threadIdx.x >> 6);
+  const int tile = (slot % groups) * kMfmaWaves + wave_index();
   if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
   cost_tile_mfma<NW, MASK>(descL, maskL, descR, W, H, dmax, disp, nullptr, nullptr, v,
                            tile * kMfmaTX);
@@ -1679,7 +1702,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
   const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int v = xcd + kXcds * (slot / groups);
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_index();
   const int tile = (slot % groups) * kMfmaWaves + wave;
   if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
   cost_tile_mfma<NW, MASK, true>(descL, maskL, descR, W, H, dmax, disp, cost,
@@ -1800,7 +1823,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_cost_wta_mfma_long(
   const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int v = xcd + kXcds * (slot / groups);
-  const int tile = (slot % groups) * kMfmaWaves + (threadIdx.x >> 6);
+  const int tile = (slot % groups) * kMfmaWaves + wave_index();
   if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
   cost_tile_mfma_long<MASK>(descL, maskL, descR, W, nw, dmax, disp, v, tile * kMfmaTX);
 }
@@ -2031,7 +2054,7 @@ __global__ __launch_bounds__(64 * kVoteWaves) void k_vote_refine(
     const int32_t *__restrict__ fallback, int W, int H, int dmax, int radius, float lambda_c,
     float lambda_e, int32_t *__restrict__ out) {
   extern __shared__ float votes[];  // [kVoteWaves][dmax]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const long long x = (long long)blockIdx.x * kVoteWaves + wave;
   const bool live = x < (long long)W * H;
   const int u = live ? (int)(x % W) : 0, v = live ? (int)(x / W) : 0;
@@ -2115,17 +2138,6 @@ __global__ __launch_bounds__(64 * kVoteWaves) void k_vote_refine(
 // Stages run one after another on the stream, so a stage only reads what the
 // previous stages completed; no workgroup ever waits for another.
 // ===========================================================================
-
-// A wave-uniform value pinned to scalar registers.
-__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-template <typename T>
-__device__ __forceinline__ T *uniform(T *p) {
-  const uint64_t x = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
-  const uint32_t hi =
-      static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x >> 32)));
-  return reinterpret_cast<T *>((static_cast<uint64_t>(hi) << 32) | lo);
-}
 
 // Largest i in [0, npairs) with start[i] <= t (start[npairs] > t).
 __device__ __forceinline__ int owner(const int *start, int npairs, int t) {
