@@ -826,10 +826,7 @@ __device__ __forceinline__ void describe_mask_tile(uint32_t *tile, int *row_next
 }
 
 template <int NW, int TW, int TH>
-// Six waves per SIMD: at n = 1024 the kernel then keeps 80 registers and
-// spills a few outside the search (0.127 -> 0.122 ms on a 450x375 view,
-// unchanged on 1400x1100); other n fit without spills.
-__global__ __launch_bounds__(kDescThreads, 6) void k_describe_mask(
+__global__ __launch_bounds__(kDescThreads) void k_describe_mask(
     const uint32_t *__restrict__ packed, int W, int H, DescribeConsts c,
     uint64_t *__restrict__ desc, uint64_t *__restrict__ mask) {
   extern __shared__ uint32_t tile[];
