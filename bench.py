@@ -650,6 +650,8 @@ def traffic_for(kernel, cfg):
 def cpu_baseline(scene, pat, p, budget_s=10.0):
     """The oracle (as it stands) on the host cores: whole pairs of the same
     workload, repeated until about budget_s seconds of CPU work."""
+    import numpy as np
+
     import oracle
     threads = len(os.sched_getaffinity(0))
     oracle.set_threads(threads)
@@ -661,10 +663,31 @@ def cpu_baseline(scene, pat, p, budget_s=10.0):
         reps += 1
     oracle.set_threads(1)
     H, W = scene.left.shape[:2]
-    return {"value": reps * W * H * p["dmax"] / t, "unit": "evals/s", "cores": threads,
-            "kind": "oracle", "seconds": round(t, 3),
-            "sample": f"{reps} full {W}x{H} pair(s) (dmax {p['dmax']}, n {p['n']}), all steps, "
-                      f"{threads} OpenMP threads over rows"}
+    out = {"value": reps * W * H * p["dmax"] / t, "unit": "evals/s", "cores": threads,
+           "kind": "oracle", "seconds": round(t, 3),
+           "sample": f"{reps} full {W}x{H} pair(s) (dmax {p['dmax']}, n {p['n']}), all steps, "
+                     f"{threads} OpenMP threads over rows"}
+    # one thread pinned to one core, on the top rows of the same pair (about
+    # 1.5e6 evaluations; every row costs the same), the median of three runs
+    rows = max(1, min(H, int(1.5e6 // (W * p["dmax"]))))
+    left = np.ascontiguousarray(scene.left[:rows])
+    right = np.ascontiguousarray(scene.right[:rows])
+    cores = sorted(os.sched_getaffinity(0))
+    times = []
+    try:
+        os.sched_setaffinity(0, {cores[0]})
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.match(left, right, pat, p["dmax"], want_cost=p["want_cost"])
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, set(cores))
+    t1 = sorted(times)[1]
+    out["single_core"] = {"value": W * rows * p["dmax"] / t1, "unit": "evals/s", "cores": 1,
+                          "seconds": round(t1, 3),
+                          "sample": f"the top {rows} rows of the pair ({W}x{rows}, dmax {p['dmax']}), "
+                                    f"median of 3 runs, one thread pinned to core {cores[0]}"}
+    return out
 
 
 def main():
