@@ -1717,6 +1717,10 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
 // slices, then runs every right block q over them, adding into block q's
 // accumulator, which lives across the passes (nine blocks at dmax 256:
 // 144 registers, which the compiler keeps in the accumulator registers).
+// Within a pass, block q + 1's right words load 16 bytes at a time while
+// block q's products run, so the matrix cores do not wait on memory; the
+// few values that do not fit the 256 vector registers go to spare
+// accumulator registers, not to scratch memory.
 // The encoding is cost_tile_mfma's; with n up to 4096 the sums reach 16 n,
 // so the key ranks acc / 8 = n + sum v b (exact: every product is 8 v b).
 // ===========================================================================
@@ -1758,6 +1762,8 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
         a_operands(aw[s], mw[s], h, A[s]);
       }
     }
+    uint32_t bw[kSlices];  // right words of the block being multiplied
+    load_slices<kLongPassWords>(rowR + (size_t)right_px(0) * nw + w0, bw);
 #pragma unroll
     for (int q = 0; q < kLongMaxBlocks; ++q) {
       if (q < nq) {  // uniform
@@ -1766,8 +1772,12 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
         uint32_t bmask[4];
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) bmask[q4] = ones << q4;
-        uint32_t bw[kSlices];
-        load_slices<kLongPassWords>(rowR + (size_t)right_px(q) * nw + w0, bw);
+        // the next block's words of this pass load as these are used up,
+        // as in cost_tile_mfma (right_px clamps, so after the last block
+        // the load stays in the row and its words go unused)
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(1))) u32x4 *GlobalU4;
+        const GlobalU4 next = (GlobalU4)(rowR + (size_t)right_px(q + 1) * nw + w0);
 #pragma unroll
         for (int s = 0; s < kSlices; ++s) {
           const uint32_t by = bw[s] >> (4 * h);
@@ -1775,6 +1785,14 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
 #pragma unroll
           for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(by & bmask[q4]);
           acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[q], 0, 0, 0);
+          if ((s & 3) == 3) {
+            const u32x4 x = next[s / 4];
+            bw[s - 3] = x[0];
+            bw[s - 2] = x[1];
+            bw[s - 1] = x[2];
+            bw[s] = x[3];
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
     }
