@@ -1427,8 +1427,7 @@ __global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restr
 }
 
 // ===========================================================================
-// Masked cost + WTA on the matrix cores, without a cost volume, n = 64 NW
-// bits, NW in {1, 2, 4, 8, 16}.
+// Masked cost + WTA on the matrix cores, n = 64 NW bits.
 //
 // The masked Hamming distance of Eq. 8 is a dot product.  For bits a (B_L),
 // m (Phi_L) and b (B_R), m (a ^ b) = m a + m (1 - 2a) b, so
@@ -1437,23 +1436,25 @@ __global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restr
 // popcount(a & m) is fixed per left pixel and cannot move its minimum over
 // d, so the WTA ranks n + sum_i v_i b_i (in [0, 2n]) instead.  For one row,
 // these sums for a tile of 32 left pixels against a block of 32 right pixels
-// are one 32 x 32 integer matrix product over the n bits: left v as int8
-// rows, right bits as int8 columns.  v_mfma_i32_32x32x32_i8 takes 32 bits
-// per step; lane (c, h) = (l % 32, l / 32) supplies 16 bits of the step's
-// 32-bit slice, one byte per bit, for left pixel u0 + c (A operand, kept in
-// registers for the whole tile) and right pixel r0 + c (B operand, expanded
-// from the packed words at each step).  Which bit sits in which byte is free
-// as long as A and B agree: byte r of dword q holds bit 8r + 4h + q.  B keeps
-// that bit where it is, (x >> 4h) & (0x01010101 << q) (byte value 2^q, one
-// AND per dword), and A carries v (8 >> q), so every product is 8 v b and
-// the accumulator, started at 8n, ranks 8 (n + sum v b).  Right block q
-// holds the pixels u0 - 32q + j, so entry (i, j) is disparity 32q + i - j and
-// the blocks q = 0 .. Q-1 cover [0, dmax).  The accumulator gives lane (c, h)
+// are one 32 x 32 matrix product over the n bits: left v as rows, right bits
+// as columns.  Lane (c, h) = (l % 32, l / 32) supplies the bits of left
+// pixel u0 + c (A operand, kept in registers) and of right pixel r0 + c (B
+// operand, expanded from the packed words for each product); the two lane
+// halves share out the bits of each product.  Which bit sits in which
+// operand slot is free as long as A and B agree.  Right block q holds the
+// pixels u0 - 32q + j, so entry (i, j) is disparity 32q + i - j and the
+// blocks q = 0 .. Q-1 cover [0, dmax).  The accumulator gives lane (c, h)
 // row 8(e/4) + 4h + e%4 of column c in its element e; the lane keeps the
-// running minimum of the key (sum << 16) | d per element, and a butterfly
+// running minimum of the key (sum << 16) + d per element, and a butterfly
 // over the 32 columns ends the WTA with the lowest d among equal costs.
-// Everything is exact integer arithmetic, so the winners equal the bitwise
-// kernel's.
+// Every sum is exact, so the winners equal the bitwise kernel's.
+//
+// Two operand encodings.  int8 (v_mfma_i32_32x32x32_i8, the long-string
+// kernel): 32 bits per product, lane half h taking 16 of every 32-bit slice,
+// one byte per bit: byte r of dword q holds bit 8r + 4h + q.  B keeps that
+// bit where it is, (x >> 4h) & (0x01010101 << q) (byte value 2^q, one AND per
+// dword), and A carries v (8 >> q), so every product is 8 v b.  fp4
+// (cost_tile_mfma, n <= 1024): described there.
 // ===========================================================================
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
@@ -1517,6 +1518,73 @@ __device__ __forceinline__ void a_operands(uint32_t aw, uint32_t mw, int h, v4i3
 // the volume (dmax x 32 costs) is assembled in LDS.
 constexpr int kMfmaVolMaxD = 256;
 
+// ---------------------------------------------------------------------------
+// The same products on the fp4 matrix cores.  v_mfma_scale_f32_32x32x64_f8f6f4
+// with e2m1 operands (and unit scales) takes 64 bits of the strings per
+// product, at the int8 product's issue cost, so lane (c, h) supplies a whole
+// 32-bit chunk: chunk h NW + k of the string in product k.  An e2m1 nibble
+// with one bit set is 0.5, 1 or 2 (bit 0, 1, 2) or a sign (bit 3).  B dword t
+// keeps the right bits 4j + t of the chunk where they are (nibble j worth
+// 0.5, 1, 2 for t = 0, 1, 2: one AND), and dword 3 takes bits 4j + 3 one
+// place down (worth 2).  A dword t carries v / (B's value) for the same bits:
+// magnitude 2, 1, 0.5, 0.5 (nibble bit 2, 1, 0, 0) with the sign bit for
+// v = -1.  Every product is v b exactly, every partial sum is a small
+// integer, so the fp32 sums are exact.  With 2^23 + n added to a block's
+// sum (fp32 steps by 1 there) the bit pattern is 0x4b000000 + (n + sum v b),
+// and its low 16 bits shifted up give the key's cost half.
+// ---------------------------------------------------------------------------
+typedef int v8i32 __attribute__((ext_vector_type(8)));
+typedef float v16f32 __attribute__((ext_vector_type(16)));
+
+// The four A dwords of one 32-bit chunk: a = B_L bits, m = Phi_L bits.
+__device__ __forceinline__ void a_nibbles(uint32_t a, uint32_t m, v4i32 &A) {
+  // m & a restricted to one bit of every nibble (0x80: x & y & z)
+  const uint32_t n0 = __builtin_amdgcn_bitop3_b32(m, a, 0x11111111u, 0x80);
+  const uint32_t n1 = __builtin_amdgcn_bitop3_b32(m, a, 0x22222222u, 0x80);
+  const uint32_t n2 = __builtin_amdgcn_bitop3_b32(m, a, 0x44444444u, 0x80);
+  const uint32_t n3 = __builtin_amdgcn_bitop3_b32(m, a, 0x88888888u, 0x80);
+  A[0] = static_cast<int>(((m & 0x11111111u) << 2) | (n0 << 3));  // 2, sign
+  A[1] = static_cast<int>((m & 0x22222222u) | (n1 << 2));         // 1, sign
+  A[2] = static_cast<int>(((m >> 2) & 0x11111111u) | (n2 << 1));  // 0.5, sign
+  A[3] = static_cast<int>(((m >> 3) & 0x11111111u) | n3);         // 0.5, sign
+}
+
+__device__ __forceinline__ v16f32 mfma_fp4(const v4i32 &A, const v4i32 &B, const v16f32 &C) {
+  constexpr int kE2M1 = 4, kUnitScale = 127;  // operand format; E8M0 2^0
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+      __builtin_shufflevector(A, A, 0, 1, 2, 3, -1, -1, -1, -1),
+      __builtin_shufflevector(B, B, 0, 1, 2, 3, -1, -1, -1, -1), C, kE2M1, kE2M1, 0,
+      kUnitScale, 0, kUnitScale);
+}
+
+// The lane's NW 32-bit chunks of one string: chunks h NW .. h NW + NW - 1 of
+// the 2 NW at p (16 bytes at a time when NW >= 4).
+template <int NW>
+__device__ __forceinline__ void load_chunks(const uint64_t *p, int h, uint32_t *out) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  typedef const __attribute__((address_space(1))) u32x4 *GlobalU4;
+  typedef const __attribute__((address_space(1))) u32x2 *GlobalU2;
+  typedef const __attribute__((address_space(1))) uint32_t *GlobalU1;
+  const uint32_t *q = reinterpret_cast<const uint32_t *>(p) + h * NW;
+  if constexpr (NW >= 4) {
+#pragma unroll
+    for (int i = 0; i < NW / 4; ++i) {
+      const u32x4 x = ((GlobalU4)q)[i];
+      out[4 * i] = x[0];
+      out[4 * i + 1] = x[1];
+      out[4 * i + 2] = x[2];
+      out[4 * i + 3] = x[3];
+    }
+  } else if constexpr (NW == 2) {
+    const u32x2 x = *(GlobalU2)q;
+    out[0] = x[0];
+    out[1] = x[1];
+  } else {
+    out[0] = *(GlobalU1)q;
+  }
+}
+
 // One wave: the 32 left pixels of row v from u0.  With VOL, `slab` is the
 // wave's LDS (dmax x 32 int16): each cost goes there first, at [d][i], and
 // the slab leaves as whole 64-byte rows of cost[d][v][u0 .. u0 + 31].
@@ -1527,37 +1595,43 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
                                                int H, int dmax, int32_t *__restrict__ disp,
                                                int16_t *__restrict__ cost, int16_t *slab, int v,
                                                int u0) {
-  constexpr int kSlices = 2 * NW;  // 32-bit slices of a string
   const int lane = threadIdx.x & 63;
   const int c = lane & 31, h = lane >> 5;
-  int am = 0;  // popcount(a & m) of the lane's left pixel (volume only)
+  int am = 0;  // popcount(a & m) of the lane's half of its left pixel (volume only)
 
-  // A operands of the lane's left pixel.  Loads
-  // are unconditional from a clamped pixel (16 bytes at a time; every
-  // string is 8-byte aligned, and 16-byte aligned when NW is even) and
-  // zeroed afterwards, so no load sits behind a branch.
+  // A operands of the lane's left pixel.  Loads are unconditional from a
+  // clamped pixel and zeroed afterwards, so no load sits behind a branch.
   const int ua = u0 + c;
   const bool has_a = ua < W;
   const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
-  v4i32 A[kSlices];
+  v4i32 A[NW];
   {
-    uint32_t aw[kSlices], mw[kSlices];
-    load_slices<NW>(descL + pa_off, aw);
-    if (MASK) load_slices<NW>(maskL + pa_off, mw);
+    uint32_t aw[NW], mw[NW];
+    load_chunks<NW>(descL + pa_off, h, aw);
+    if (MASK) load_chunks<NW>(maskL + pa_off, h, mw);
 #pragma unroll
-    for (int s = 0; s < kSlices; ++s) {
-      if (!MASK) mw[s] = 0xffffffffu;
-      if (!has_a) aw[s] = mw[s] = 0;
-      if (VOL) am += __builtin_popcount(aw[s] & mw[s]);
-      a_operands(aw[s], mw[s], h, A[s]);
+    for (int k = 0; k < NW; ++k) {
+      if (!MASK) mw[k] = 0xffffffffu;
+      if (!has_a) aw[k] = mw[k] = 0;
+      if (VOL) am += __builtin_popcount(aw[k] & mw[k]);
+      a_nibbles(aw[k], mw[k], A[k]);
     }
   }
-  // costs: C = popcount(a & m) + sum v b = am_row + acc / 8 - n
+  // costs: C = popcount(a & m) + sum v b = am_row + (accumulator bits & 0xffff) - n
   int cbase[16];
   if (VOL) {
+    am += __shfl_xor(am, 32);  // both halves of the pixel
 #pragma unroll
     for (int e = 0; e < 16; ++e) cbase[e] = __shfl(am, 8 * (e / 4) + 4 * h + (e % 4)) - 64 * NW;
   }
+  // The key of element e in block q is ((n + sum v b) << 16) + 32 q +
+  // kKeyBias.  The rest of d = 32 q + row(e) - c is the lane's own and the
+  // same in every block, so it joins the low half once, after the blocks
+  // (the bias keeps the low half from borrowing: row(e) - c >= -31).  Within
+  // an element a lower key is a lower cost or, on equal costs, a lower q, d.
+  constexpr uint32_t kKeyBias = 64;
+  constexpr float kBias = 8388608.0f + 64.0f * NW;  // 2^23 + n
+  const v16f32 zero = {};
   uint32_t best[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) best[e] = 0xffffffffu;
@@ -1565,81 +1639,90 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
   const int nq = (dmax + 30) / kMfmaTX + 1;  // right blocks
   // The lane's right pixel of block q, clamped into the row for loading.
   auto right_px = [&](int q) { return min(max(u0 - kMfmaTX * q + c, 0), W - 1); };
-  uint32_t bw[kSlices];
-  load_slices<NW>(rowR + (size_t)right_px(0) * NW, bw);
-  for (int q = 0; q < nq; ++q) {
-    // The next block's words load into bw as this block's products use
-    // them up (16 bytes per four slices), so that they have the whole block
-    // to arrive.  The loads are unconditional (after the last block they
-    // read a clamped pixel of the row again) and through global pointers,
-    // so that each wait covers exactly the load it needs.
+  uint32_t bw[NW];
+  load_chunks<NW>(rowR + (size_t)right_px(0) * NW, h, bw);
+  // One right block; with `fast` every entry of the block is valid.
+  auto block = [&](int q, auto fast) {
+    // The next block's chunks load into bw as this block's products use them
+    // up (16 bytes per four products), so that they have the whole block to
+    // arrive.  The loads are unconditional (after the last block they read
+    // a clamped pixel of the row again).
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     typedef const __attribute__((address_space(1))) u32x4 *GlobalU4;
-    const GlobalU4 next = (GlobalU4)(rowR + (size_t)right_px(q + 1) * NW);
+    const uint64_t *next_px = rowR + (size_t)right_px(q + 1) * NW;
+    const GlobalU4 next = (GlobalU4)(reinterpret_cast<const uint32_t *>(next_px) + h * NW);
     const int rb = u0 - kMfmaTX * q + c;  // the lane's right pixel
-    // B dword q4 keeps bits q4 + 8r of the shifted word in place (byte
-    // value 2^q4), one AND each; a missing right pixel gives B = 0.
-    const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;
-    uint32_t bmask[4];
+    // a missing right pixel gives B = 0
+    const uint32_t ones = (rb >= 0 && rb < W) ? 0xffffffffu : 0u;
+    const uint32_t b0 = ones & 0x11111111u, b1 = ones & 0x22222222u, b2 = ones & 0x44444444u;
+    v16f32 acc;
 #pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) bmask[q4] = ones << q4;
-    v16i32 acc;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 8 * 64 * NW;  // 8 (n + sum v b) >= 0
-#pragma unroll
-    for (int s = 0; s < kSlices; ++s) {
-      const uint32_t by = bw[s] >> (4 * h);
+    for (int k = 0; k < NW; ++k) {
+      const uint32_t x = bw[k];
       v4i32 B;
-#pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(by & bmask[q4]);
-      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc, 0, 0, 0);
-      if constexpr (NW % 2 == 0) {
-        if ((s & 3) == 3) {
-          const u32x4 x = next[s / 4];
-          bw[s - 3] = x[0];
-          bw[s - 2] = x[1];
-          bw[s - 1] = x[2];
-          bw[s] = x[3];
-          // keep the load here: scheduled freely, all of them sink to the
-          // end of the block and arrive late
+      B[0] = static_cast<int>(x & b0);
+      B[1] = static_cast<int>(x & b1);
+      B[2] = static_cast<int>(x & b2);
+      B[3] = static_cast<int>((x >> 1) & b2);
+      acc = mfma_fp4(A[k], B, k == 0 ? zero : acc);
+      if constexpr (NW >= 4) {
+        if ((k & 3) == 3) {
+          const u32x4 y = next[k / 4];
+          bw[k - 3] = y[0];
+          bw[k - 2] = y[1];
+          bw[k - 1] = y[2];
+          bw[k] = y[3];
+          // keep the load here: scheduled freely, the loads move to one end
+          // of the block
           __builtin_amdgcn_sched_barrier(0);
         }
-      } else if (s == kSlices - 1) {  // NW = 1: one 8-byte word
-        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        typedef const __attribute__((address_space(1))) u32x2 *GlobalU2;
-        const u32x2 x = *(GlobalU2)(rowR + (size_t)right_px(q + 1));
-        bw[0] = x[0];
-        bw[1] = x[1];
+      } else if (k == NW - 1) {
+        load_chunks<NW>(next_px, h, bw);
       }
     }
     // d of element e is dbase + row(e); valid when 0 <= d < dmax and the
-    // right pixel exists (u - d = rb >= 0).  Blocks whose every entry is
-    // valid (the wave-uniform test below) skip the per-element checks.
+    // right pixel exists (u - d = rb >= 0).
     const int dbase = kMfmaTX * q - c;
+    const uint32_t key_lo = kMfmaTX * q + kKeyBias;  // wave-uniform
+    uint32_t sum[16];  // n + sum v b in the low 16 bits
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sum[e] = __float_as_uint(acc[e] + kBias);
     if (VOL) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
         if (d >= 0 && d < dmax)
           slab[d * kSlabPitch + 8 * (e / 4) + 4 * h + (e % 4)] = static_cast<int16_t>(
-              rb >= 0 ? cbase[e] + (acc[e] >> 3) : kInvalidCost);
+              rb >= 0 ? cbase[e] + static_cast<int>(sum[e] & 0xffffu)
+                      : kInvalidCost);
       }
     }
-    if (q >= 1 && kMfmaTX * q + kMfmaTX - 1 < dmax && u0 - kMfmaTX * q >= 0) {
+    if constexpr (decltype(fast)::value) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
-        best[e] = min(best[e], (static_cast<uint32_t>(acc[e]) << 16) | static_cast<uint32_t>(d));
-      }
+      for (int e = 0; e < 16; ++e)
+        best[e] = min(best[e], (sum[e] << 16) + key_lo);
     } else {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
-        const uint32_t key = (static_cast<uint32_t>(acc[e]) << 16) | static_cast<uint32_t>(d);
+        const uint32_t key = (sum[e] << 16) + key_lo;
         if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
       }
     }
-  }
+  };
+  // Every entry of block q is valid for 1 <= q <= q_fast (d in [1, dmax),
+  // right pixel in the row); the condition only weakens as q grows, so the
+  // blocks run as three loops without per-block branches.
+  const int q_fast =
+      min(nq - 1, min(dmax >= kMfmaTX ? (dmax - kMfmaTX) / kMfmaTX : 0, u0 / kMfmaTX));
+  block(0, std::false_type{});
+  for (int q = 1; q <= q_fast; ++q) block(q, std::true_type{});
+  for (int q = max(q_fast + 1, 1); q < nq; ++q) block(q, std::false_type{});
+  // the lane's part of d (an element no block updated stays above every
+  // real key: 0xffffffff less at most 95)
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    best[e] += static_cast<uint32_t>(8 * (e / 4) + 4 * h + (e % 4) - c) - kKeyBias;
   // WTA across the 32 columns of each half.
 #pragma unroll
   for (int off = 16; off >= 1; off >>= 1) {
@@ -1721,7 +1804,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
 // block q's products run, so the matrix cores do not wait on memory; the
 // few values that do not fit the 256 vector registers go to spare
 // accumulator registers, not to scratch memory.
-// The encoding is cost_tile_mfma's; with n up to 4096 the sums reach 16 n,
+// The encoding is the int8 one; with n up to 4096 the sums reach 16 n,
 // so the key ranks acc / 8 = n + sum v b (exact: every product is 8 v b).
 // ===========================================================================
 constexpr int kLongPassWords = 8;
@@ -1749,7 +1832,7 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[q][e] = 8 * 64 * nw;  // 8 (n + sum v b) >= 0
   for (int w0 = 0; w0 < nw; w0 += kLongPassWords) {
-    // A operands of this pass (cost_tile_mfma's encoding)
+    // A operands of this pass (int8 encoding)
     v4i32 A[kSlices];
     {
       uint32_t aw[kSlices], mw[kSlices];
