@@ -1448,16 +1448,11 @@ __global__ __launch_bounds__(64, 2) void k_cost_wta_fast(const uint64_t *__restr
 // running minimum of the key (sum << 16) + d per element, and a butterfly
 // over the 32 columns ends the WTA with the lowest d among equal costs.
 // Every sum is exact, so the winners equal the bitwise kernel's.
-//
-// Two operand encodings.  int8 (v_mfma_i32_32x32x32_i8, the long-string
-// kernel): 32 bits per product, lane half h taking 16 of every 32-bit slice,
-// one byte per bit: byte r of dword q holds bit 8r + 4h + q.  B keeps that
-// bit where it is, (x >> 4h) & (0x01010101 << q) (byte value 2^q, one AND per
-// dword), and A carries v (8 >> q), so every product is 8 v b.  fp4
-// (cost_tile_mfma, n <= 1024): described there.
+// The products are fp4 ones (below).  An earlier int8 form
+// (v_mfma_i32_32x32x32_i8, one byte per bit, 32 bits per product) took
+// twice the products and about twice the vector instructions per bit.
 // ===========================================================================
 typedef int v4i32 __attribute__((ext_vector_type(4)));
-typedef int v16i32 __attribute__((ext_vector_type(16)));
 
 constexpr int kMfmaTX = 32;     // left pixels per wave
 // Row pitch (int16) of a wave's volume slab [d][pixel]: an odd number of
@@ -1466,60 +1461,12 @@ constexpr int kMfmaTX = 32;     // left pixels per wave
 constexpr int kSlabPitch = kMfmaTX + 2;
 constexpr int kMfmaWaves = 4;   // tiles (waves) per workgroup, consecutive in a row
 
-// The 2 NW 32-bit slices of one string (NW 64-bit words at p).
-template <int NW>
-__device__ __forceinline__ void load_slices(const uint64_t *p, uint32_t *out) {
-  if constexpr (NW % 2 == 0) {
-#pragma unroll
-    for (int i = 0; i < NW / 2; ++i) {
-      const uint4 x = reinterpret_cast<const uint4 *>(p)[i];
-      out[4 * i] = x.x;
-      out[4 * i + 1] = x.y;
-      out[4 * i + 2] = x.z;
-      out[4 * i + 3] = x.w;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      const uint2 x = reinterpret_cast<const uint2 *>(p)[i];
-      out[2 * i] = x.x;
-      out[2 * i + 1] = x.y;
-    }
-  }
-}
-
-// The four A dwords of one 32-bit slice for lane half h: byte r of dword q
-// is v w for bit 8r + 4h + q, with v = +1 for (m, !a), -1 for (m, a), 0 for
-// !m, and w = 8 >> q (the B byte of the same bit holds 2^q, so every
-// product is 8 v b).  Nibble h of p = m & !a and of n = m & a are
-// interleaved per byte (n3 p3 n2 p2 n1 p1 n0 p0), so that bits 2q, 2q + 1
-// form a v_perm_b32 selector 2 n + p into the bytes (0, w, -w) of a
-// constant.  v_bitop3_b32 immediates are truth tables over the operands
-// 0xf0, 0xcc, 0xaa: 0x20 = x & !y & z, 0x80 = x & y & z, 0xca = x ? y : z.
-__device__ __forceinline__ void a_operands(uint32_t aw, uint32_t mw, int h, v4i32 &A) {
-  const uint32_t as = aw >> (4 * h), ms = mw >> (4 * h);
-  const uint32_t p = __builtin_amdgcn_bitop3_b32(ms, as, 0x0f0f0f0fu, 0x20);
-  const uint32_t n = __builtin_amdgcn_bitop3_b32(ms, as, 0x0f0f0f0fu, 0x80);
-  const uint32_t x0 = (n << 4) | p;  // n3 n2 n1 n0 p3 p2 p1 p0
-  // swap bit pairs 5:4 and 3:2, then bits 6 and 5, 2 and 1
-  const uint32_t x1 = __builtin_amdgcn_bitop3_b32(
-      0x30303030u, x0 << 2, __builtin_amdgcn_bitop3_b32(0x0c0c0c0cu, x0 >> 2, x0, 0xca), 0xca);
-  const uint32_t x2 = __builtin_amdgcn_bitop3_b32(
-      0x44444444u, x1 << 1, __builtin_amdgcn_bitop3_b32(0x22222222u, x1 >> 1, x1, 0xca), 0xca);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    constexpr uint32_t kW[4] = {8, 4, 2, 1};
-    const uint32_t table = ((256u - kW[q]) << 16) | (kW[q] << 8);  // bytes 0, w, -w, 0
-    A[q] = static_cast<int>(__builtin_amdgcn_perm(table, table, (x2 >> (2 * q)) & 0x03030303u));
-  }
-}
-
 // Largest dmax of the matrix-core kernel with a volume: the wave's slab of
 // the volume (dmax x 32 costs) is assembled in LDS.
 constexpr int kMfmaVolMaxD = 256;
 
 // ---------------------------------------------------------------------------
-// The same products on the fp4 matrix cores.  v_mfma_scale_f32_32x32x64_f8f6f4
+// fp4 products.  v_mfma_scale_f32_32x32x64_f8f6f4
 // with e2m1 operands (and unit scales) takes 64 bits of the strings per
 // product, at the int8 product's issue cost, so lane (c, h) supplies a whole
 // 32-bit chunk: chunk h NW + k of the string in product k.  An e2m1 nibble
@@ -1793,19 +1740,17 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
 }
 
 // ===========================================================================
-// Matrix-core cost + WTA for long descriptors: nw a multiple of 16 above 16
-// (n = 2048, 3072, 4096), no volume, dmax <= 256.  The A operands of a
-// tile's 32 left pixels for all n bits would need 8 nw registers a lane, so
-// the bits go in passes of 512 (8 words): a pass builds A for its 16
-// slices, then runs every right block q over them, adding into block q's
-// accumulator, which lives across the passes (nine blocks at dmax 256:
-// 144 registers, which the compiler keeps in the accumulator registers).
-// Within a pass, block q + 1's right words load 16 bytes at a time while
-// block q's products run, so the matrix cores do not wait on memory; the
-// few values that do not fit the 256 vector registers go to spare
-// accumulator registers, not to scratch memory.
-// The encoding is the int8 one; with n up to 4096 the sums reach 16 n,
-// so the key ranks acc / 8 = n + sum v b (exact: every product is 8 v b).
+// Matrix-core cost + WTA for long descriptors: nw a multiple of 8 above 16
+// (n = 1536, 2048, ..., 4096), no volume, dmax <= 256, with cost_tile_mfma's
+// fp4 products.  The A operands of a tile's 32 left pixels for all n bits
+// would need 2 nw registers a lane, so the bits go in passes of 512 (8
+// words): a pass builds A for its 16 chunks (8 a lane half), then runs every
+// right block q over them, adding into block q's accumulator, which lives
+// across the passes (nine blocks at dmax 256: 144 registers, which the
+// compiler keeps in the accumulator registers).  Within a pass, block
+// q + 1's right words load 16 bytes at a time while block q's products run.
+// The sums stay exact integers (|sum v b| <= n); the key takes n + sum v b
+// from the low mantissa bits of the sum plus 2^23 + n, as cost_tile_mfma.
 // ===========================================================================
 constexpr int kLongPassWords = 8;
 constexpr int kLongMaxBlocks = 9;  // right blocks, (dmax + 30) / 32 + 1, at dmax 256
@@ -1817,7 +1762,7 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
                                                     const uint64_t *__restrict__ descR, int W,
                                                     int nw, int dmax, int32_t *__restrict__ disp,
                                                     int v, int u0) {
-  constexpr int kSlices = 2 * kLongPassWords;  // 32-bit slices of a pass
+  constexpr int kChunks = kLongPassWords;  // 32-bit chunks of a pass per lane half
   const int lane = threadIdx.x & 63;
   const int c = lane & 31, h = lane >> 5;
   const int ua = u0 + c;
@@ -1826,54 +1771,57 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
   const uint64_t *rowR = descR + (size_t)v * W * nw;
   const int nq = (dmax + 30) / kMfmaTX + 1;  // right blocks, <= kLongMaxBlocks
   auto right_px = [&](int q) { return min(max(u0 - kMfmaTX * q + c, 0), W - 1); };
-  v16i32 acc[kLongMaxBlocks];
+  v16f32 acc[kLongMaxBlocks];
 #pragma unroll
   for (int q = 0; q < kLongMaxBlocks; ++q)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[q][e] = 8 * 64 * nw;  // 8 (n + sum v b) >= 0
+    for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
   for (int w0 = 0; w0 < nw; w0 += kLongPassWords) {
-    // A operands of this pass (int8 encoding)
-    v4i32 A[kSlices];
+    // A operands of this pass: the lane half's chunks 2 w0 + 8 h .. + 7
+    v4i32 A[kChunks];
     {
-      uint32_t aw[kSlices], mw[kSlices];
-      load_slices<kLongPassWords>(descL + pa_off + w0, aw);
-      if (MASK) load_slices<kLongPassWords>(maskL + pa_off + w0, mw);
+      uint32_t aw[kChunks], mw[kChunks];
+      load_chunks<kChunks>(descL + pa_off + w0, h, aw);
+      if (MASK) load_chunks<kChunks>(maskL + pa_off + w0, h, mw);
 #pragma unroll
-      for (int s = 0; s < kSlices; ++s) {
-        if (!MASK) mw[s] = 0xffffffffu;
-        if (!has_a) aw[s] = mw[s] = 0;
-        a_operands(aw[s], mw[s], h, A[s]);
+      for (int k = 0; k < kChunks; ++k) {
+        if (!MASK) mw[k] = 0xffffffffu;
+        if (!has_a) aw[k] = mw[k] = 0;
+        a_nibbles(aw[k], mw[k], A[k]);
       }
     }
-    uint32_t bw[kSlices];  // right words of the block being multiplied
-    load_slices<kLongPassWords>(rowR + (size_t)right_px(0) * nw + w0, bw);
+    uint32_t bw[kChunks];  // right chunks of the block being multiplied
+    load_chunks<kChunks>(rowR + (size_t)right_px(0) * nw + w0, h, bw);
 #pragma unroll
     for (int q = 0; q < kLongMaxBlocks; ++q) {
       if (q < nq) {  // uniform
         const int rb = u0 - kMfmaTX * q + c;
-        const uint32_t ones = (rb >= 0 && rb < W) ? 0x01010101u : 0u;
-        uint32_t bmask[4];
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) bmask[q4] = ones << q4;
-        // the next block's words of this pass load as these are used up,
+        const uint32_t ones = (rb >= 0 && rb < W) ? 0xffffffffu : 0u;
+        const uint32_t b0 = ones & 0x11111111u, b1 = ones & 0x22222222u,
+                       b2 = ones & 0x44444444u;
+        // the next block's chunks of this pass load as these are used up,
         // as in cost_tile_mfma (right_px clamps, so after the last block
         // the load stays in the row and its words go unused)
         typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
         typedef const __attribute__((address_space(1))) u32x4 *GlobalU4;
-        const GlobalU4 next = (GlobalU4)(rowR + (size_t)right_px(q + 1) * nw + w0);
+        const GlobalU4 next = (GlobalU4)(reinterpret_cast<const uint32_t *>(
+                                             rowR + (size_t)right_px(q + 1) * nw + w0) +
+                                         h * kChunks);
 #pragma unroll
-        for (int s = 0; s < kSlices; ++s) {
-          const uint32_t by = bw[s] >> (4 * h);
+        for (int k = 0; k < kChunks; ++k) {
+          const uint32_t x = bw[k];
           v4i32 B;
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4) B[q4] = static_cast<int>(by & bmask[q4]);
-          acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[q], 0, 0, 0);
-          if ((s & 3) == 3) {
-            const u32x4 x = next[s / 4];
-            bw[s - 3] = x[0];
-            bw[s - 2] = x[1];
-            bw[s - 1] = x[2];
-            bw[s] = x[3];
+          B[0] = static_cast<int>(x & b0);
+          B[1] = static_cast<int>(x & b1);
+          B[2] = static_cast<int>(x & b2);
+          B[3] = static_cast<int>((x >> 1) & b2);
+          acc[q] = mfma_fp4(A[k], B, acc[q]);
+          if ((k & 3) == 3) {
+            const u32x4 y = next[k / 4];
+            bw[k - 3] = y[0];
+            bw[k - 2] = y[1];
+            bw[k - 1] = y[2];
+            bw[k] = y[3];
             __builtin_amdgcn_sched_barrier(0);
           }
         }
@@ -1882,6 +1830,7 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
   }
   // WTA: element e of block q is d = 32 q - c + row(e), valid when
   // 0 <= d < dmax and the right pixel exists
+  const float bias = 8388608.0f + 64.0f * static_cast<float>(nw);  // 2^23 + n
   uint32_t best[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) best[e] = 0xffffffffu;
@@ -1893,7 +1842,7 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int d = dbase + 8 * (e / 4) + 4 * h + (e % 4);
-        const uint32_t key = (static_cast<uint32_t>(acc[q][e] >> 3) << 16) | static_cast<uint32_t>(d);
+        const uint32_t key = (__float_as_uint(acc[q][e] + bias) << 16) | static_cast<uint32_t>(d);
         if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
       }
     }
