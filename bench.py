@@ -28,11 +28,11 @@ sys.path.insert(0, ROOT)
 CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
 ALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ          # 3.93e13 lane-ops/s
 HBM_PEAK_BPS = 8.0e12
-MFMA_I8_PEAK_OPS = 5.0e15                                  # dense int8 matrix ops/s
+MFMA_FP4_PEAK_OPS = 10.1e15   # dense fp4 matrix ops/s (the cost kernels' products)
 
 
 def measured_peaks(args):
-    """Vector-ALU, int8 matrix and HBM rates measured on this GPU by the
+    """Vector-ALU, int8 and fp4 matrix and HBM rates measured on this GPU by the
     library's probe kernels (None with --no-peaks)."""
     if args.no_peaks:
         return None
@@ -41,6 +41,7 @@ def measured_peaks(args):
     return {"valu_int32_TOPs": round(p["valu_int32_ops"] / 1e12, 3),
             "valu_addxor_TOPs": round(p["valu_addxor_ops"] / 1e12, 3),
             "mfma_i8_TOPs": round(p["mfma_i8_ops"] / 1e12, 1),
+            "mfma_fp4_TOPs": round(p["mfma_fp4_ops"] / 1e12, 1),
             "hbm_read_GBps": round(p["hbm_read_bps"] / 1e9, 1),
             "hbm_copy_GBps": round(p["hbm_copy_bps"] / 1e9, 1),
             "compute_units": p["compute_units"]}
@@ -51,7 +52,7 @@ def with_measured_peak(roof, peaks):
     it reached; `peak` and `frac` stay the published MI355X figures."""
     if roof is None or peaks is None:
         return roof
-    key = {"alu": "valu_int32_TOPs", "mfma": "mfma_i8_TOPs", "hbm": "hbm_copy_GBps"}[roof["bound"]]
+    key = {"alu": "valu_int32_TOPs", "mfma": "mfma_fp4_TOPs", "hbm": "hbm_copy_GBps"}[roof["bound"]]
     roof["peak_measured"] = peaks[key]
     roof["frac_of_measured"] = round(roof["achieved"] / peaks[key], 4)
     return roof
@@ -231,8 +232,8 @@ def bench_batch(args):
         # two SADs, max, ~10 threshold-search compares and delta per pair)
         # and the right view's descriptor (n: tau per pair)
         "batch_describe": ("alu", pixels * 16 * n, ALU_PEAK_OPS, "TOP/s", 1e12),
-        # per evaluation an n-bit int8 dot product on the matrix cores (2 n ops)
-        "batch_cost": ("mfma", evals * 2 * n, MFMA_I8_PEAK_OPS, "TOP/s", 1e12),
+        # per evaluation an n-term fp4 dot product on the matrix cores (2 n ops)
+        "batch_cost": ("mfma", evals * 2 * n, MFMA_FP4_PEAK_OPS, "TOP/s", 1e12),
         # per pixel and view: 3 B of RGB in, 4 B of packed colour out
         "batch_color": ("hbm", pixels * 2 * 7, HBM_PEAK_BPS, "GB/s", 1e9),
     }
@@ -517,8 +518,8 @@ def bench_nsweep(args):
                      # VALU peak; above 1 when the matrix cores beat that roofline
                      "cost_wta_valu_popcount_equiv_frac": evals * (n / 16 + 1) / (ms_cost / 1e3) /
                      ALU_PEAK_OPS,
-                     "cost_wta_frac_of_mfma_i8_peak": (evals * 2 * n / (ms_cost / 1e3) /
-                                                       MFMA_I8_PEAK_OPS) if on_mfma else None})
+                     "cost_wta_frac_of_mfma_fp4_peak": (evals * 2 * n / (ms_cost / 1e3) /
+                                                        MFMA_FP4_PEAK_OPS) if on_mfma else None})
         print(json.dumps({"progress": "nsweep", **rows[-1]}), flush=True)
         ctx.close()
     # least-squares slope of time against n (the paper states linear cost in n)
@@ -821,7 +822,7 @@ def main():
         "describe_right": npx * 1 * n,          # per pair: tau
         "cost_wta": evals * (n // 16 + 1),      # per eval: n/32 x (bitop3 + bcnt) + min
     }
-    # On the matrix cores an evaluation is an n-term int8 dot product (2n
+    # On the matrix cores an evaluation is an n-term fp4 dot product (2n
     # ops); the bitwise count above stays as the VALU-popcount equivalent.
     mfma = cost_on_matrix_cores(ctx.tuning(), n, dmax, p["want_cost"])
     bytes_ = {"color_left": npx * 7, "color_right": npx * 7}
@@ -830,7 +831,7 @@ def main():
         ent = {"ms": round(ms, 5)}
         if name == "cost_wta" and mfma:
             ent.update(bound="mfma", achieved_Tops=evals * 2 * n / (ms / 1e3) / 1e12,
-                       frac=evals * 2 * n / (ms / 1e3) / MFMA_I8_PEAK_OPS,
+                       frac=evals * 2 * n / (ms / 1e3) / MFMA_FP4_PEAK_OPS,
                        valu_popcount_equiv_frac=ops[name] / (ms / 1e3) / ALU_PEAK_OPS)
         elif name in ops:
             ent.update(bound="alu", achieved_Tops=ops[name] / (ms / 1e3) / 1e12,
@@ -844,8 +845,8 @@ def main():
     if dom == "cost_wta" and mfma:
         achieved = evals * 2 * n / (dms / 1e3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
-                "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s",
-                "frac": round(achieved * 1e12 / MFMA_I8_PEAK_OPS, 4),
+                "peak": MFMA_FP4_PEAK_OPS / 1e12, "unit": "TOP/s",
+                "frac": round(achieved * 1e12 / MFMA_FP4_PEAK_OPS, 4),
                 "traffic": traffic_for(dom, cfg)}
     elif dom in ops:
         achieved = ops[dom] / (dms / 1e3) / 1e12

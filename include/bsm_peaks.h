@@ -4,7 +4,8 @@
  * The roofline fractions of the BSM kernels are quoted against the
  * published MI355X figures (32-bit vector lane operations: 256 CUs x 2.4 GHz
  * x 64 per CU and clock, the unpacked rate behind the 78.6 TFLOP/s fp64
- * vector figure; dense int8 matrix ops 5.0 POP/s; HBM3E 8 TB/s).  This call
+ * vector figure; dense int8 matrix ops 5.0 POP/s; dense fp4 matrix ops
+ * 10.1 POP/s; HBM3E 8 TB/s).  This call
  * measures what the same units reach on the device at hand, with kernels
  * that do nothing but that work, so that a fraction can also be read
  * against an attainable ceiling.  It is a measurement utility beside the
@@ -33,6 +34,10 @@ typedef struct bsm_peaks {
     /* Dense int8 matrix operations per second: v_mfma_i32_32x32x32_i8,
        two operations per multiply-add (32 x 32 x 32 x 2 per instruction). */
     double mfma_i8_ops;
+    /* Dense fp4 (e2m1) matrix operations per second at unit scale:
+       v_mfma_scale_f32_32x32x64_f8f6f4, 32 x 32 x 64 x 2 per instruction,
+       the product the matrix-core cost kernels issue. */
+    double mfma_fp4_ops;
     /* HBM bytes per second of a streaming read (16-byte loads) of a buffer
        of hbm_bytes, far larger than the L2 and last-level caches. */
     double hbm_read_bps;

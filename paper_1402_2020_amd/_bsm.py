@@ -62,7 +62,7 @@ class ServeCounters(C.Structure):
 
 class Peaks(C.Structure):
     _fields_ = [("valu_int32_ops", C.c_double), ("valu_addxor_ops", C.c_double),
-                ("mfma_i8_ops", C.c_double),
+                ("mfma_i8_ops", C.c_double), ("mfma_fp4_ops", C.c_double),
                 ("hbm_read_bps", C.c_double), ("hbm_copy_bps", C.c_double),
                 ("compute_units", C.c_int32)]
 

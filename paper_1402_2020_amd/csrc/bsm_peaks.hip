@@ -12,6 +12,8 @@ namespace {
 
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
+typedef int v8i32 __attribute__((ext_vector_type(8)));
+typedef float v16f32 __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;
 constexpr int kValuIters = 4096;
@@ -19,6 +21,7 @@ constexpr int kValuPerIter = 32;   // instructions per loop iteration, per lane
 constexpr int kMfmaIters = 2048;
 constexpr int kMfmaChains = 4;     // independent accumulators per wave
 constexpr double kMfmaOps = 32.0 * 32.0 * 32.0 * 2.0;
+constexpr double kMfmaFp4Ops = 32.0 * 32.0 * 64.0 * 2.0;
 
 // Four independent chains, 32 instructions per iteration written out in
 // assembly so that none is folded or removed.  MIX: the kinds the describe
@@ -83,6 +86,32 @@ __global__ __launch_bounds__(kThreads) void k_peak_mfma(int seed, int iters,
 #pragma unroll
     for (int e = 0; e < 16; ++e) s += acc[j][e];
   out[gid] = s;
+}
+
+// The same with v_mfma_scale_f32_32x32x64_f8f6f4 on e2m1 (fp4) operands at
+// unit scale (E8M0 127), the product the matrix-core cost kernels issue;
+// operands use the low four dwords.
+__global__ __launch_bounds__(kThreads) void k_peak_mfma_fp4(int seed, int iters,
+                                                            int *__restrict__ out) {
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const v8i32 a = {seed ^ gid, gid, seed, 0x22222222, 0, 0, 0, 0};
+  const v8i32 b = {gid * 3, seed ^ 0x15151515, 0x21212121, gid, 0, 0, 0, 0};
+  v16f32 acc[kMfmaChains];
+#pragma unroll
+  for (int j = 0; j < kMfmaChains; ++j)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[j][e] = static_cast<float>(j + e);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < kMfmaChains; ++j)
+      acc[j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc[j], 4, 4, 0, 127, 0, 127);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < kMfmaChains; ++j)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) s += acc[j][e];
+  out[gid] = static_cast<int>(s);
 }
 
 // Grid-stride streaming read, four 16-byte loads in flight per lane.
@@ -188,7 +217,7 @@ extern "C" bsm_status bsm_measure_peaks(int device, size_t hbm_bytes, int reps, 
   const size_t n16 = hbm_bytes / 16, half16 = n16 / 2;
   const uint4 *src = static_cast<const uint4 *>(p.buf);
   uint4 *dst = static_cast<uint4 *>(p.buf) + half16;
-  float t_valu, t_addxor, t_mfma, t_read, t_copy;
+  float t_valu, t_addxor, t_mfma, t_fp4, t_read, t_copy;
   if ((e = best_ms([&] {
          hipLaunchKernelGGL(k_peak_valu<true>, dim3(valu_blocks), dim3(kThreads), 0, p.s,
                             0x9e3779b9u, kValuIters, static_cast<uint32_t *>(p.out));
@@ -201,6 +230,10 @@ extern "C" bsm_status bsm_measure_peaks(int device, size_t hbm_bytes, int reps, 
          hipLaunchKernelGGL(k_peak_mfma, dim3(mfma_blocks), dim3(kThreads), 0, p.s, 0x1402,
                             kMfmaIters, static_cast<int *>(p.out));
        }, &t_mfma)) != hipSuccess ||
+      (e = best_ms([&] {
+         hipLaunchKernelGGL(k_peak_mfma_fp4, dim3(mfma_blocks), dim3(kThreads), 0, p.s, 0x1402,
+                            kMfmaIters, static_cast<int *>(p.out));
+       }, &t_fp4)) != hipSuccess ||
       (e = best_ms([&] {
          hipLaunchKernelGGL(k_peak_read, dim3(mem_blocks), dim3(kThreads), 0, p.s, src, n16,
                             static_cast<uint32_t *>(p.out));
@@ -216,6 +249,7 @@ extern "C" bsm_status bsm_measure_peaks(int device, size_t hbm_bytes, int reps, 
   out->valu_int32_ops = valu_lane_ops / (t_valu * 1e-3);
   out->valu_addxor_ops = valu_lane_ops / (t_addxor * 1e-3);
   out->mfma_i8_ops = mfma_ops / (t_mfma * 1e-3);
+  out->mfma_fp4_ops = mfma_ops / kMfmaOps * kMfmaFp4Ops / (t_fp4 * 1e-3);
   out->hbm_read_bps = (double)n16 * 16 / (t_read * 1e-3);
   out->hbm_copy_bps = (double)half16 * 16 * 2 / (t_copy * 1e-3);
   out->compute_units = cus;

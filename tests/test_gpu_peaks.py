@@ -23,6 +23,8 @@ PUBLISHED = {
     "valu_addxor_ops": 256 * 128 * 2.4e9,
     # dense int8 matrix operations per second
     "mfma_i8_ops": 5.0e15,
+    # dense fp4 (e2m1) matrix operations per second
+    "mfma_fp4_ops": 10.1e15,
     # HBM3E
     "hbm_read_bps": 8.0e12,
     "hbm_copy_bps": 8.0e12,
