@@ -243,8 +243,7 @@ bsm_status batch_persistent(bsm_ctx *ctx, BatchState &b, const DeviceTables &dt,
     horder[i] = order[i];
     int counts[kBatchQueues];
     batch_tile_counts(p.width, p.height, use_mask, p.cost != nullptr, dt.tune.desc_tile_w,
-                      dt.tune.batch_tile_h,
-                      counts);
+                      dt.tune.batch_tile_h, dt.tune.cost_mfma, counts);
     for (int q = 0; q < kBatchQueues; ++q) hstart[q * n1 + i + 1] = hstart[q * n1 + i] + counts[q];
   }
   BatchWork *hw = reinterpret_cast<BatchWork *>(h + table_bytes);

@@ -141,9 +141,10 @@ hipError_t launch_cost_wta(const uint64_t *descL, const uint64_t *maskL,
 hipError_t launch_batch(const BatchLaunch &bl, const DeviceTables &t, int use_mask,
                         hipStream_t s);
 bool batch_supported(int nw);
-// Tiles per stage of one pair, as the batch kernels number them.
+// Tiles per stage of one pair, as the batch kernels number them (cost_mfma:
+// the matrix-core cost kernel takes the pairs without a volume).
 void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
-                       int desc_tile_h, int counts[kBatchQueues]);
+                       int desc_tile_h, int cost_mfma, int counts[kBatchQueues]);
 
 // ---- batch (bsm_batch.cpp) --------------------------------------------------
 struct BatchState;

@@ -2388,15 +2388,14 @@ __global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restric
   }
 }
 
-// The no-volume cost queues on the matrix cores.  An item is a 128-pixel
-// row tile, and each wave pulls items on its own and runs their four 32-pixel
-// tiles: the waves of a workgroup share nothing, so they never wait for one
-// another at a barrier (at two waves per SIMD an idle wave costs half the
-// SIMD).  The next item is claimed before the current one runs.
+// The no-volume cost queues on the matrix cores.  An item is one 32-pixel
+// row tile, and each wave pulls items on its own: the waves of a workgroup
+// share nothing, so they never wait for one another at a barrier (at two
+// waves per SIMD an idle wave costs half the SIMD).  The next item is
+// claimed before the current one runs.
 template <int NW, bool MASK>
 __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
     const BatchWork *__restrict__ bw) {
-  static_assert(kCostTX == kMfmaWaves * kMfmaTX, "an item is four matrix-core tiles");
   const int home = blockIdx.x % kXcds;
   const int n = bw->npairs;
   for (int qi = 0; qi < kXcds; ++qi) {
@@ -2416,17 +2415,12 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
       }
       const BatchPair &p = bw->pairs[bw->order[i]];
       const int W = uniform(p.W);
-      const int tiles = (W + kCostTX - 1) / kCostTX;
+      const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
       const int local = cur - start[i];
       const int v = x + kXcds * (local / tiles);
-      const int u_item = (local % tiles) * kCostTX;
-      for (int k = 0; k < kMfmaWaves; ++k) {
-        const int u0 = u_item + k * kMfmaTX;
-        if (u0 < W)
-          cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
-                                   uniform(p.H), uniform(p.dmax), uniform(p.disp), nullptr,
-                                   nullptr, v, u0);
-      }
+      cost_tile_mfma<NW, MASK>(uniform(p.descL), uniform(p.maskL), uniform(p.descR), W,
+                               uniform(p.H), uniform(p.dmax), uniform(p.disp), nullptr, nullptr,
+                               v, (local % tiles) * kMfmaTX);
       cur = wave_value(next);
     }
   }
@@ -2657,7 +2651,7 @@ int describe_right_cols(int radius) {
 }
 
 void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_w,
-                       int desc_tile_h, int counts[kBatchQueues]) {
+                       int desc_tile_h, int cost_mfma, int counts[kBatchQueues]) {
   counts[kQueueColor] =
       2 * ((W + kColorTX - 1) / kColorTX) * ((H + kBatchColorTY - 1) / kBatchColorTY);
   counts[kQueueDescribeMask] =
@@ -2665,11 +2659,15 @@ void batch_tile_counts(int W, int H, int use_mask, int want_cost, int desc_tile_
                : 0;
   counts[kQueueDescribe] =
       (use_mask ? 1 : 2) * ((W + kRightTW - 1) / kRightTW) * ((H + kRightTH - 1) / kRightTH);
+  // The bitwise kernels take 128-pixel items; the matrix-core kernel takes
+  // single 32-pixel tiles, so that the rows open at once on an XCD (whose
+  // right descriptors its L2 must hold) are as few as in one pair's launch.
   const int tiles = (W + kCostTX - 1) / kCostTX;
+  const int cost_tiles = cost_mfma ? (W + kMfmaTX - 1) / kMfmaTX : tiles;
   for (int x = 0; x < kXcds; ++x) {
-    const int rows_tiles = H > x ? tiles * ((H - x + kXcds - 1) / kXcds) : 0;
-    counts[kQueueCost0 + x] = want_cost ? 0 : rows_tiles;
-    counts[kQueueCostVol0 + x] = want_cost ? rows_tiles : 0;
+    const int rows = H > x ? (H - x + kXcds - 1) / kXcds : 0;
+    counts[kQueueCost0 + x] = want_cost ? 0 : cost_tiles * rows;
+    counts[kQueueCostVol0 + x] = want_cost ? tiles * rows : 0;
   }
 }
 
