@@ -1706,19 +1706,159 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
   }
 }
 
+// Two adjacent tiles in one wave, left pixels u0 .. u0 + 63 (both tiles
+// start inside the row).  Right block b (pixels u0 + 32 - 32 b + j) is block
+// q = b of tile 1 and block q = b - 1 of tile 0, so its B operands, expanded
+// once, feed the products of both tiles: blocks b = 0 .. nq, the first for
+// tile 1 alone and the last for tile 0 alone.  Keys as in cost_tile_mfma.
+template <int NW, bool MASK>
+__device__ __forceinline__ void a_operands_of(const uint64_t *__restrict__ descL,
+                                              const uint64_t *__restrict__ maskL, int W, int v,
+                                              int ua, int h, v4i32 *A) {
+  const bool has_a = ua < W;
+  const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
+  uint32_t aw[NW], mw[NW];
+  load_chunks<NW>(descL + pa_off, h, aw);
+  if (MASK) load_chunks<NW>(maskL + pa_off, h, mw);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    if (!MASK) mw[k] = 0xffffffffu;
+    if (!has_a) aw[k] = mw[k] = 0;
+    a_nibbles(aw[k], mw[k], A[k]);
+  }
+}
+
+template <int NW, bool MASK>
+__device__ __forceinline__ void cost_tile_pair_mfma(const uint64_t *__restrict__ descL,
+                                                    const uint64_t *__restrict__ maskL,
+                                                    const uint64_t *__restrict__ descR, int W,
+                                                    int dmax, int32_t *__restrict__ disp, int v,
+                                                    int u0) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 31, h = lane >> 5;
+  v4i32 A0[NW], A1[NW];
+  a_operands_of<NW, MASK>(descL, maskL, W, v, u0 + c, h, A0);
+  a_operands_of<NW, MASK>(descL, maskL, W, v, u0 + kMfmaTX + c, h, A1);
+  constexpr uint32_t kKeyBias = 64;
+  constexpr float kBias = 8388608.0f + 64.0f * NW;  // 2^23 + n
+  const v16f32 zero = {};
+  uint32_t best0[16], best1[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) best0[e] = best1[e] = 0xffffffffu;
+  const uint64_t *rowR = descR + (size_t)v * W * NW;
+  const int nq = (dmax + 30) / kMfmaTX + 1;  // right blocks of each tile
+  const int u1 = u0 + kMfmaTX;                // tile 1's first pixel
+  auto right_px = [&](int b) { return min(max(u1 - kMfmaTX * b + c, 0), W - 1); };
+  uint32_t bw[NW];
+  load_chunks<NW>(rowR + (size_t)right_px(0) * NW, h, bw);
+  // tile t's entries of one block into its running minima
+  auto fold = [&](const v16f32 &acc, uint32_t *best, int q, int rb, auto fast) {
+    const uint32_t key_lo = kMfmaTX * q + kKeyBias;  // wave-uniform
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const uint32_t key = (__float_as_uint(acc[e] + kBias) << 16) + key_lo;
+      if constexpr (decltype(fast)::value) {
+        best[e] = min(best[e], key);
+      } else {
+        const int d = kMfmaTX * q - c + 8 * (e / 4) + 4 * h + (e % 4);
+        if (d >= 0 && d < dmax && rb >= 0) best[e] = min(best[e], key);
+      }
+    }
+  };
+  // Right block b for tile 0 (USE0: q = b - 1) and tile 1 (USE1: q = b);
+  // with `fast` every entry of both is valid.
+  auto block = [&](int b, auto use0, auto use1, auto fast) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) u32x4 *GlobalU4;
+    const uint64_t *next_px = rowR + (size_t)right_px(b + 1) * NW;
+    const GlobalU4 next = (GlobalU4)(reinterpret_cast<const uint32_t *>(next_px) + h * NW);
+    const int rb = u1 - kMfmaTX * b + c;  // the lane's right pixel (both tiles)
+    const uint32_t ones = (rb >= 0 && rb < W) ? 0xffffffffu : 0u;
+    const uint32_t b0 = ones & 0x11111111u, b1 = ones & 0x22222222u, b2 = ones & 0x44444444u;
+    v16f32 acc0, acc1;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const uint32_t x = bw[k];
+      v4i32 B;
+      B[0] = static_cast<int>(x & b0);
+      B[1] = static_cast<int>(x & b1);
+      B[2] = static_cast<int>(x & b2);
+      B[3] = static_cast<int>((x >> 1) & b2);
+      if constexpr (decltype(use1)::value) acc1 = mfma_fp4(A1[k], B, k == 0 ? zero : acc1);
+      if constexpr (decltype(use0)::value) acc0 = mfma_fp4(A0[k], B, k == 0 ? zero : acc0);
+      if constexpr (NW >= 4) {
+        if ((k & 3) == 3) {
+          const u32x4 y = next[k / 4];
+          bw[k - 3] = y[0];
+          bw[k - 2] = y[1];
+          bw[k - 1] = y[2];
+          bw[k] = y[3];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else if (k == NW - 1) {
+        load_chunks<NW>(next_px, h, bw);
+      }
+    }
+    if constexpr (decltype(use1)::value) fold(acc1, best1, b, rb, fast);
+    if constexpr (decltype(use0)::value) fold(acc0, best0, b - 1, rb, fast);
+  };
+  // Every entry of both tiles is valid for 2 <= b <= b_fast (tile 0's
+  // q = b - 1 >= 1, d < dmax for tile 1's q = b, right pixels in the row);
+  // the condition only weakens as b grows.
+  const int b_fast =
+      min(nq - 1, min(dmax >= kMfmaTX ? (dmax - kMfmaTX) / kMfmaTX : 0, u1 / kMfmaTX));
+  block(0, std::false_type{}, std::true_type{}, std::false_type{});
+  if (nq > 1) block(1, std::true_type{}, std::true_type{}, std::false_type{});
+  for (int b = 2; b <= b_fast; ++b) block(b, std::true_type{}, std::true_type{}, std::true_type{});
+  for (int b = max(b_fast + 1, 2); b < nq; ++b)
+    block(b, std::true_type{}, std::true_type{}, std::false_type{});
+  block(nq, std::true_type{}, std::false_type{}, std::false_type{});
+  // the lane's part of d, then the WTA across the 32 columns of each half
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const uint32_t part = static_cast<uint32_t>(8 * (e / 4) + 4 * h + (e % 4) - c) - kKeyBias;
+    best0[e] += part;
+    best1[e] += part;
+  }
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      best0[e] = min(best0[e], static_cast<uint32_t>(__shfl_xor(static_cast<int>(best0[e]), off)));
+      best1[e] = min(best1[e], static_cast<uint32_t>(__shfl_xor(static_cast<int>(best1[e]), off)));
+    }
+  }
+  if (c < 16) {
+    uint32_t key0 = best0[0], key1 = best1[0];
+#pragma unroll
+    for (int e = 1; e < 16; ++e)
+      if (c == e) {
+        key0 = best0[e];
+        key1 = best1[e];
+      }
+    const int u = u0 + 8 * (c / 4) + 4 * h + (c % 4);
+    if (u < W) disp[(size_t)v * W + u] = static_cast<int32_t>(key0 & 0xffffu);
+    if (u + kMfmaTX < W) disp[(size_t)v * W + u + kMfmaTX] = static_cast<int32_t>(key1 & 0xffffu);
+  }
+}
+
 template <int NW, bool MASK>
 __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
     const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
     const uint64_t *__restrict__ descR, int W, int H, int dmax, int32_t *__restrict__ disp) {
-  // XCD-aware order (see k_cost_wta_fast), in groups of kMfmaWaves tiles.
-  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
-  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
+  // XCD-aware order (see k_cost_wta_fast), in groups of kMfmaWaves waves of
+  // two tiles each.
+  const int pairs = (W + 2 * kMfmaTX - 1) / (2 * kMfmaTX);
+  const int groups = (pairs + kMfmaWaves - 1) / kMfmaWaves;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int v = xcd + kXcds * (slot / groups);
-  const int tile = (slot % groups) * kMfmaWaves + wave_index();
-  if (v >= H || tile >= tiles) return;  // whole wave; no barrier follows
-  cost_tile_mfma<NW, MASK>(descL, maskL, descR, W, H, dmax, disp, nullptr, nullptr, v,
-                           tile * kMfmaTX);
+  const int pair = (slot % groups) * kMfmaWaves + wave_index();
+  if (v >= H || pair >= pairs) return;  // whole wave; no barrier follows
+  const int u0 = pair * 2 * kMfmaTX;
+  if (u0 + kMfmaTX < W)
+    cost_tile_pair_mfma<NW, MASK>(descL, maskL, descR, W, dmax, disp, v, u0);
+  else
+    cost_tile_mfma<NW, MASK>(descL, maskL, descR, W, H, dmax, disp, nullptr, nullptr, v, u0);
 }
 
 // With the volume (dmax <= kMfmaVolMaxD): dynamic LDS of kMfmaWaves slabs.
@@ -2522,6 +2662,8 @@ hipError_t launch_cost_mfma(const uint64_t *descL, const uint64_t *maskL, const 
                          descL, maskL, descR, W, H, dmax, disp, cost);
     return hipGetLastError();
   }
+  const int pairs = (W + 2 * kMfmaTX - 1) / (2 * kMfmaTX);
+  grid = dim3(kXcds * ((pairs + kMfmaWaves - 1) / kMfmaWaves) * ((H + kXcds - 1) / kXcds));
   if (maskL)
     hipLaunchKernelGGL((k_cost_wta_mfma<NW, true>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
                        maskL, descR, W, H, dmax, disp);
