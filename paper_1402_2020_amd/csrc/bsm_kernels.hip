@@ -1886,9 +1886,11 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_vol(
 // would need 2 nw registers a lane, so the bits go in passes of 512 (8
 // words): a pass builds A for its 16 chunks (8 a lane half), then runs every
 // right block q over them, adding into block q's accumulator, which lives
-// across the passes (nine blocks at dmax 256: 144 registers, which the
-// compiler keeps in the accumulator registers).  Within a pass, block
-// q + 1's right words load 16 bytes at a time while block q's products run.
+// across the passes (nine blocks at dmax 256: 144 registers).  Within a
+// pass, block q + 1's right words load 16 bytes at a time while block q's
+// products run.  Bounded to two waves per SIMD (256 registers a lane, one
+// value spilled), which hide the chains of dependent products far better
+// than one.
 // The sums stay exact integers (|sum v b| <= n); the key takes n + sum v b
 // from the low mantissa bits of the sum plus 2^23 + n, as cost_tile_mfma.
 // ===========================================================================
@@ -2004,7 +2006,7 @@ __device__ __forceinline__ void cost_tile_mfma_long(const uint64_t *__restrict__
 }
 
 template <bool MASK>
-__global__ __launch_bounds__(64 * kMfmaWaves) void k_cost_wta_mfma_long(
+__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma_long(
     const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
     const uint64_t *__restrict__ descR, int W, int H, int nw, int dmax,
     int32_t *__restrict__ disp) {
@@ -2530,11 +2532,12 @@ __global__ __launch_bounds__(64, 2) void k_batch_cost(const BatchWork *__restric
 
 // The no-volume cost queues on the matrix cores.  An item is one 32-pixel
 // row tile, and each wave pulls items on its own: the waves of a workgroup
-// share nothing, so they never wait for one another at a barrier (at two
-// waves per SIMD an idle wave costs half the SIMD).  The next item is
-// claimed before the current one runs.
+// share nothing, so they never wait for one another at a barrier.  The
+// next item is claimed before the current one runs.  Bounded to three waves
+// per SIMD (168 registers, nothing spilled to memory), which hide more of
+// each block's chain of dependent products than two.
 template <int NW, bool MASK>
-__global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_batch_cost_mfma(
+__global__ __launch_bounds__(64 * kMfmaWaves, 3) void k_batch_cost_mfma(
     const BatchWork *__restrict__ bw) {
   const int home = blockIdx.x % kXcds;
   const int n = bw->npairs;
