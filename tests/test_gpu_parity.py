@@ -202,6 +202,10 @@ MFMA_CASES = [
     (450, 2, 16, 60, True),
     (259, 3, 16, 256, True),   # largest dmax with the volume on the matrix cores, odd W
     (77, 3, 4, 40, False),     # odd W, Eq. 4
+    # tile pairs of the single-pair kernel: the block range without checks is
+    # empty for the first pair and one or two blocks long for later ones
+    (200, 2, 16, 96, True),
+    (190, 3, 8, 129, False),
     # long descriptors: matrix cores in passes of 512 bits (no volume,
     # dmax <= 256), the word-chunked bitwise kernel otherwise
     (130, 3, 32, 64, True),    # n = 2048
