@@ -1532,6 +1532,29 @@ __device__ __forceinline__ void load_chunks(const uint64_t *p, int h, uint32_t *
   }
 }
 
+// The A operands of left pixel ua of row v for the lane's half h of the
+// chunks (zero past the row's end, where the loads read a clamped pixel, so
+// no load sits behind a branch); with VOL also popcount(a & m) of that half.
+template <int NW, bool MASK, bool VOL = false>
+__device__ __forceinline__ void a_operands_of(const uint64_t *__restrict__ descL,
+                                              const uint64_t *__restrict__ maskL, int W, int v,
+                                              int ua, int h, v4i32 *A, int *am = nullptr) {
+  const bool has_a = ua < W;
+  const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
+  uint32_t aw[NW], mw[NW];
+  load_chunks<NW>(descL + pa_off, h, aw);
+  if (MASK) load_chunks<NW>(maskL + pa_off, h, mw);
+  int pc = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    if (!MASK) mw[k] = 0xffffffffu;
+    if (!has_a) aw[k] = mw[k] = 0;
+    if (VOL) pc += __builtin_popcount(aw[k] & mw[k]);
+    a_nibbles(aw[k], mw[k], A[k]);
+  }
+  if (VOL) *am = pc;
+}
+
 // One wave: the 32 left pixels of row v from u0.  With VOL, `slab` is the
 // wave's LDS (dmax x 32 int16): each cost goes there first, at [d][i], and
 // the slab leaves as whole 64-byte rows of cost[d][v][u0 .. u0 + 31].
@@ -1545,25 +1568,8 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
   const int lane = threadIdx.x & 63;
   const int c = lane & 31, h = lane >> 5;
   int am = 0;  // popcount(a & m) of the lane's half of its left pixel (volume only)
-
-  // A operands of the lane's left pixel.  Loads are unconditional from a
-  // clamped pixel and zeroed afterwards, so no load sits behind a branch.
-  const int ua = u0 + c;
-  const bool has_a = ua < W;
-  const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
   v4i32 A[NW];
-  {
-    uint32_t aw[NW], mw[NW];
-    load_chunks<NW>(descL + pa_off, h, aw);
-    if (MASK) load_chunks<NW>(maskL + pa_off, h, mw);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      if (!MASK) mw[k] = 0xffffffffu;
-      if (!has_a) aw[k] = mw[k] = 0;
-      if (VOL) am += __builtin_popcount(aw[k] & mw[k]);
-      a_nibbles(aw[k], mw[k], A[k]);
-    }
-  }
+  a_operands_of<NW, MASK, VOL>(descL, maskL, W, v, u0 + c, h, A, &am);
   // costs: C = popcount(a & m) + sum v b = am_row + (accumulator bits & 0xffff) - n
   int cbase[16];
   if (VOL) {
@@ -1712,23 +1718,6 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
 // once, feed the products of both tiles: blocks b = 0 .. nq, the first for
 // tile 1 alone and the last for tile 0 alone.  Keys as in cost_tile_mfma.
 template <int NW, bool MASK>
-__device__ __forceinline__ void a_operands_of(const uint64_t *__restrict__ descL,
-                                              const uint64_t *__restrict__ maskL, int W, int v,
-                                              int ua, int h, v4i32 *A) {
-  const bool has_a = ua < W;
-  const size_t pa_off = ((size_t)v * W + (has_a ? ua : W - 1)) * NW;
-  uint32_t aw[NW], mw[NW];
-  load_chunks<NW>(descL + pa_off, h, aw);
-  if (MASK) load_chunks<NW>(maskL + pa_off, h, mw);
-#pragma unroll
-  for (int k = 0; k < NW; ++k) {
-    if (!MASK) mw[k] = 0xffffffffu;
-    if (!has_a) aw[k] = mw[k] = 0;
-    a_nibbles(aw[k], mw[k], A[k]);
-  }
-}
-
-template <int NW, bool MASK>
 __device__ __forceinline__ void cost_tile_pair_mfma(const uint64_t *__restrict__ descL,
                                                     const uint64_t *__restrict__ maskL,
                                                     const uint64_t *__restrict__ descR, int W,
@@ -1847,14 +1836,14 @@ __global__ __launch_bounds__(64 * kMfmaWaves, 2) void k_cost_wta_mfma(
     const uint64_t *__restrict__ descL, const uint64_t *__restrict__ maskL,
     const uint64_t *__restrict__ descR, int W, int H, int dmax, int32_t *__restrict__ disp) {
   // XCD-aware order (see k_cost_wta_fast), in groups of kMfmaWaves waves of
-  // two tiles each.
-  const int pairs = (W + 2 * kMfmaTX - 1) / (2 * kMfmaTX);
-  const int groups = (pairs + kMfmaWaves - 1) / kMfmaWaves;
+  // two tiles each (a duo).
+  const int duos = (W + 2 * kMfmaTX - 1) / (2 * kMfmaTX);
+  const int groups = (duos + kMfmaWaves - 1) / kMfmaWaves;
   const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
   const int v = xcd + kXcds * (slot / groups);
-  const int pair = (slot % groups) * kMfmaWaves + wave_index();
-  if (v >= H || pair >= pairs) return;  // whole wave; no barrier follows
-  const int u0 = pair * 2 * kMfmaTX;
+  const int duo = (slot % groups) * kMfmaWaves + wave_index();
+  if (v >= H || duo >= duos) return;  // whole wave; no barrier follows
+  const int u0 = duo * 2 * kMfmaTX;
   if (u0 + kMfmaTX < W)
     cost_tile_pair_mfma<NW, MASK>(descL, maskL, descR, W, dmax, disp, v, u0);
   else
@@ -2647,10 +2636,10 @@ hipError_t launch_cost_fast_dc(const uint64_t *descL, const uint64_t *maskL,
 template <int NW>
 hipError_t launch_cost_mfma(const uint64_t *descL, const uint64_t *maskL, const uint64_t *descR,
                             int W, int H, int dmax, int32_t *disp, int16_t *cost, hipStream_t s) {
-  const int tiles = (W + kMfmaTX - 1) / kMfmaTX;
-  const int groups = (tiles + kMfmaWaves - 1) / kMfmaWaves;
-  dim3 grid(kXcds * groups * ((H + kXcds - 1) / kXcds));
+  const int rows = (H + kXcds - 1) / kXcds;  // rows per XCD
   if (cost) {
+    const int tiles = (W + kMfmaTX - 1) / kMfmaTX;  // a wave per tile
+    const dim3 grid(kXcds * ((tiles + kMfmaWaves - 1) / kMfmaWaves) * rows);
     static const hipError_t attr[2] = {
         allow_big_lds(reinterpret_cast<const void *>(k_cost_wta_mfma_vol<NW, false>)),
         allow_big_lds(reinterpret_cast<const void *>(k_cost_wta_mfma_vol<NW, true>))};
@@ -2665,8 +2654,8 @@ hipError_t launch_cost_mfma(const uint64_t *descL, const uint64_t *maskL, const 
                          descL, maskL, descR, W, H, dmax, disp, cost);
     return hipGetLastError();
   }
-  const int pairs = (W + 2 * kMfmaTX - 1) / (2 * kMfmaTX);
-  grid = dim3(kXcds * ((pairs + kMfmaWaves - 1) / kMfmaWaves) * ((H + kXcds - 1) / kXcds));
+  const int duos = (W + 2 * kMfmaTX - 1) / (2 * kMfmaTX);  // a wave per two tiles
+  const dim3 grid(kXcds * ((duos + kMfmaWaves - 1) / kMfmaWaves) * rows);
   if (maskL)
     hipLaunchKernelGGL((k_cost_wta_mfma<NW, true>), grid, dim3(64 * kMfmaWaves), 0, s, descL,
                        maskL, descR, W, H, dmax, disp);
