@@ -308,7 +308,7 @@ def bsm_drain(ctx):
 # ---- convenience layer over torch tensors --------------------------------
 
 def bsm_measure_peaks(device=0, hbm_bytes=4 << 30, reps=3):
-    """Measured vector-ALU, int8 matrix and HBM rates of the device (dict)."""
+    """Measured vector-ALU, int8 and fp4 matrix and HBM rates of the device (dict)."""
     out = Peaks()
     _check(load().bsm_measure_peaks(device, hbm_bytes, reps, C.byref(out)), "bsm_measure_peaks")
     return out.as_dict()
