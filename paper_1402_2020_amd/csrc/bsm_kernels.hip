@@ -1466,9 +1466,9 @@ constexpr int kMfmaWaves = 4;   // tiles (waves) per workgroup, consecutive in a
 constexpr int kMfmaVolMaxD = 256;
 
 // ---------------------------------------------------------------------------
-// fp4 products.  v_mfma_scale_f32_32x32x64_f8f6f4
-// with e2m1 operands (and unit scales) takes 64 bits of the strings per
-// product, at the int8 product's issue cost, so lane (c, h) supplies a whole
+// The fp4 products.  v_mfma_scale_f32_32x32x64_f8f6f4 with e2m1 operands
+// (and unit scales) takes 64 bits of the strings per product, at the issue
+// cost of a 32-bit int8 product, so lane (c, h) supplies a whole
 // 32-bit chunk: chunk h NW + k of the string in product k.  An e2m1 nibble
 // with one bit set is 0.5, 1 or 2 (bit 0, 1, 2) or a sign (bit 3).  B dword t
 // keeps the right bits 4j + t of the chunk where they are (nibble j worth
@@ -1480,7 +1480,6 @@ constexpr int kMfmaVolMaxD = 256;
 // sum (fp32 steps by 1 there) the bit pattern is 0x4b000000 + (n + sum v b),
 // and its low 16 bits shifted up give the key's cost half.
 // ---------------------------------------------------------------------------
-typedef int v8i32 __attribute__((ext_vector_type(8)));
 typedef float v16f32 __attribute__((ext_vector_type(16)));
 
 // The four A dwords of one 32-bit chunk: a = B_L bits, m = Phi_L bits.
