@@ -1569,7 +1569,8 @@ __device__ __forceinline__ void cost_tile_mfma(const uint64_t *__restrict__ desc
   int am = 0;  // popcount(a & m) of the lane's half of its left pixel (volume only)
   v4i32 A[NW];
   a_operands_of<NW, MASK, VOL>(descL, maskL, W, v, u0 + c, h, A, &am);
-  // costs: C = popcount(a & m) + sum v b = am_row + (accumulator bits & 0xffff) - n
+  // costs: C = popcount(a & m) + sum v b = am_row - n + (n + sum v b), the
+  // last term the low 16 bits of the block's sum plus 2^23 + n
   int cbase[16];
   if (VOL) {
     am += __shfl_xor(am, 32);  // both halves of the pixel
